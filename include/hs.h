@@ -1,0 +1,191 @@
+/*
+ * hs.h -- C ABI of the MI355X (gfx950) harmonic-summing library (libhs.so).
+ *
+ * The library computes the harmonic-summing module of Wang, Thiagaraj &
+ * Sinnen, "Harmonic-summing Module of SKA on FPGA -- Optimising the
+ * Irregular Memory Accesses" (arXiv:1805.12258), Sec. III:
+ *
+ *   FOP      filter-output plane, N_temp templates (rows) x N_chan bins of
+ *            power, resident in device memory before a call (Sec. IV-A
+ *            assumes the FOP is already in the accelerator's memory).
+ *   SP_m(i,j) = FOP(floor(i/m), floor(j/m))                   (Eq. 1)
+ *   HP_1 = FOP,  HP_k = HP_{k-1} + SP_k,  k = 2..N_hp          (Eq. 2)
+ *   candidate  HP_k(i,j) > TA(k,i), one threshold per row and plane.
+ *   candidate word  CL1 = F << (s_k + s_bin) | (k-1) << s_bin | B,
+ *            CL2 = power (fp32)       (Sec. III, candidate list format)
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  * Storage row r in [0, N_temp) holds template index i = r - N_temp/2
+ *    (integer division): for odd N_temp the paper's range
+ *    [-(N_temp-1)/2, (N_temp-1)/2]; for even N_temp [-N_temp/2, N_temp/2-1].
+ *    floor() is the mathematical floor, also for negative i.
+ *  * Partial sums are fp32 and formed in the order of Eq. 2 (m = 1, 2, ...,
+ *    k), each rounded: results are bitwise those of a sequential fp32 loop.
+ *  * The FOP is row-major [N_temp][ld] with ld >= N_chan elements of the
+ *    plan's storage type.  The base pointer must be 16-byte aligned and ld a
+ *    multiple of 4 (fp32) or 8 (fp16, bf16) elements; HS_ERR_INVALID
+ *    otherwise.  Reduced-precision storage holds power * input_scale;
+ *    thresholds and reported powers are in unscaled units.
+ *  * Every pointer argument except hs_plan_desc.n_chans and the host count
+ *    array of hs_check_counts is DEVICE memory owned by the caller.  The
+ *    library never frees caller memory.
+ *  * `stream` is a hipStream_t (NULL = the default stream).  Calls enqueue
+ *    work and return without waiting; the status covers argument checks and
+ *    the launch only.  Output is valid once the stream has been synchronised.
+ *  * A plan is immutable after creation and may be used from several
+ *    streams at once: all per-call state lives in caller buffers.
+ *  * No C++ exception crosses this interface.
+ */
+#ifndef HS_H
+#define HS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum hs_status {
+    HS_OK = 0,
+    HS_ERR_INVALID = -1,      /* bad argument, shape, alignment or pointer    */
+    HS_ERR_OVERFLOW = -2,     /* more candidates than the output capacity     */
+    HS_ERR_HIP = -3,          /* a HIP runtime call failed (no GPU, launch)   */
+    HS_ERR_UNSUPPORTED = -4,  /* valid request the library does not implement */
+    HS_ERR_NOMEM = -5         /* host or device allocation failed             */
+} hs_status;
+
+typedef enum hs_dtype {
+    HS_DTYPE_F32 = 0,         /* IEEE binary32 power                          */
+    HS_DTYPE_F16 = 1,         /* IEEE binary16 of power * input_scale         */
+    HS_DTYPE_BF16 = 2         /* bfloat16 of power * input_scale              */
+} hs_dtype;
+
+/* One candidate: CL1 (packed row, plane, bin) and CL2 (power), 8 bytes. */
+typedef struct hs_cand {
+    uint32_t idx;
+    float power;
+} hs_cand;
+
+typedef struct hs_plan hs_plan;
+
+typedef struct hs_plan_desc {
+    int64_t n_temp;            /* N_temp >= 1 (Sec. III: 85)                    */
+    int64_t n_chan;            /* N_chan >= 1 of a single-FOP plan (2^21);      */
+                               /* ignored when n_fops >= 1                       */
+    int32_t n_hp;              /* N_hp, 1..16 (Sec. III: 8)                      */
+    int32_t dtype;             /* hs_dtype of the stored FOP                     */
+    float input_scale;         /* stored = power * input_scale; a power of two;  */
+                               /* 0 means 1                                      */
+    int32_t n_fops;            /* 0: single FOP; >= 1: batch of n_fops FOPs      */
+    const int64_t* n_chans;    /* HOST array [n_fops]: bins of each FOP          */
+    int32_t tile_rows;         /* tuning: rows per tile, 0 = planner's choice    */
+    int32_t persistent_blocks; /* tuning: batched grid size, 0 = planner         */
+} hs_plan_desc;
+
+/* Geometry chosen by the planner (host values; no GPU needed). */
+typedef struct hs_plan_info {
+    int32_t n_temp, n_hp, dtype, n_fops;
+    int64_t n_chan_max;
+    int32_t s_row, s_k, s_bin;  /* candidate-word shifts: row << s_row,          */
+                                /* (k-1) << s_bin, field widths ceil(log2 .)     */
+    int32_t tile_bins;          /* bins per tile                                 */
+    int32_t tile_rows;          /* rows per tile                                 */
+    int32_t row_blocks;         /* tiles across the rows                         */
+    int32_t lds_bytes;          /* dynamic LDS of the fused kernel               */
+    int64_t tiles_total;        /* tiles over all FOPs                           */
+    int32_t src_rows[17];       /* src_rows[m]: distinct source rows of stretch  */
+                                /* factor m over one full-height tile            */
+    int64_t staged_words;       /* source words staged per full tile, m >= 2     */
+} hs_plan_info;
+
+/* Create a plan.  Validates the shapes (HS_ERR_INVALID: N_temp < 1, n_hp
+ * outside 1..16, unknown dtype, input_scale not a power of two, n_fops < 0,
+ * a bin count < 1, or a candidate word wider than 32 bits, i.e.
+ * ceil(log2 N_temp) + ceil(log2 N_hp) + ceil(log2 N_chan) > 32).  Host only:
+ * touches no GPU. */
+hs_status hs_plan_create(hs_plan** plan, const hs_plan_desc* desc);
+
+/* Release a plan and the device tables it owns.  NULL is accepted. */
+hs_status hs_plan_destroy(hs_plan* plan);
+
+/* Planner geometry, for inspection and tests.  Host only. */
+hs_status hs_plan_info_get(const hs_plan* plan, hs_plan_info* info);
+
+/* All harmonic planes (Eq. 1-2), materialised: hp is [n_hp][N_temp][N_chan]
+ * fp32 (plane-major, leading dimension N_chan) in unscaled units.
+ * Single-FOP plans only. */
+hs_status hs_sum(const hs_plan* plan, const void* fop, int64_t ld, float* hp, void* stream);
+
+/* Harmonic planes and threshold detection fused (Sec. III detection; the
+ * loop order of Algorithm 2, no plane is written to memory).
+ *   ta       [n_hp][N_temp] fp32 thresholds, TA(k, row), unscaled units.
+ *   out      [capacity] candidates, in no particular order.
+ *   counts   [n_hp + 1] int64: candidates of each plane, then the total.
+ *            Always the true counts, also when they exceed capacity; the
+ *            call zeroes them first.
+ * When the total exceeds capacity, `capacity` of the candidates are written
+ * (which ones is unspecified); see hs_check_counts.  Single-FOP plans only. */
+hs_status hs_detect(const hs_plan* plan, const void* fop, int64_t ld, const float* ta,
+                    hs_cand* out, int64_t capacity, int64_t* counts, void* stream);
+
+/* hs_detect over a batch of FOPs of different lengths in one launch of a
+ * persistent kernel (no host synchronisation and no allocation inside, so
+ * the call can be captured into a HIP graph).  All arrays are DEVICE arrays:
+ *   fops        [n_fops] pointers to the FOPs (each with the plan's dtype)
+ *   lds         [n_fops] leading dimensions
+ *   ta          [n_hp][N_temp], shared by every FOP
+ *   out_offsets [n_fops] first entry of each FOP's candidates in `out`
+ *   caps        [n_fops] capacity of each FOP's candidate range
+ *   counts      [n_fops][n_hp + 1] per-FOP counts as in hs_detect
+ * Alignment rules of the FOP apply to every FOP (checked on the device:
+ * misaligned FOPs are skipped and their total count is set to -1).
+ * Batched plans only. */
+hs_status hs_detect_batched(const hs_plan* plan, const void* const* fops, const int64_t* lds,
+                            const float* ta, hs_cand* out, const int64_t* out_offsets,
+                            const int64_t* caps, int64_t* counts, void* stream);
+
+/* Sort n candidates in place into the canonical order: ascending CL1 word
+ * (row, then plane, then bin; CL1 words are unique within one FOP).
+ * `work` is device scratch of at least hs_sort_workspace_bytes(n) bytes. */
+size_t hs_sort_workspace_bytes(int64_t n);
+hs_status hs_sort_candidates(hs_cand* cand, int64_t n, void* work, void* stream);
+
+/* Vector-Jacobian product of hs_sum (the transpose of Eq. 1-2): given
+ * g = dL/dHP [n_hp][N_temp][N_chan] fp32, overwrites dfop [N_temp][N_chan]
+ * fp32 with dL/dFOP in unscaled units.  `work` is device scratch of
+ * hs_backward_workspace_bytes(plan) bytes.  Deterministic: the same input
+ * gives bitwise the same output. */
+size_t hs_backward_workspace_bytes(const hs_plan* plan);
+hs_status hs_sum_backward(const hs_plan* plan, const float* g, float* dfop, void* work,
+                          void* stream);
+
+/* Log-sum-exp statistic of each plane of one FOP, recomputing the planes
+ * from the FOP (no plane is stored):
+ *   lse[k-1] = log sum_{i,j} exp(HP_k(i,j) / tau)            (fp32 out)
+ * hs_lse_backward overwrites dfop [N_temp][N_chan] fp32 with gscale times
+ * the gradient of L = sum_k tau * lse[k-1] with respect to the FOP (unscaled
+ * units), given the lse values of the forward call.  Both need `work` of
+ * hs_lse_workspace_bytes(plan) bytes. */
+size_t hs_lse_workspace_bytes(const hs_plan* plan);
+hs_status hs_lse_forward(const hs_plan* plan, const void* fop, int64_t ld, float tau, float* lse,
+                         void* work, void* stream);
+hs_status hs_lse_backward(const hs_plan* plan, const void* fop, int64_t ld, const float* lse,
+                          float tau, float gscale, float* dfop, void* work, void* stream);
+
+/* Host check of counts copied back from hs_detect: HS_ERR_OVERFLOW when
+ * counts[n_hp] > capacity, HS_OK otherwise. */
+hs_status hs_check_counts(const int64_t* counts_host, int32_t n_hp, int64_t capacity);
+
+/* Static description of a status code. */
+const char* hs_status_string(hs_status status);
+
+/* Library version string. */
+const char* hs_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HS_H */

@@ -1,0 +1,284 @@
+"""MI355X harmonic summing: Python binding of libhs.so (argument marshalling only).
+
+Every computation runs in the HIP kernels of ``libhs.so``; this module only
+turns torch tensors into device pointers, sizes and the current HIP stream
+and calls the C ABI declared in ``include/hs.h``.  The functions keep the C
+names (``hs_plan_create``, ``hs_sum``, ``hs_detect``, ...).  :class:`Plan`
+and the helpers at the bottom are conveniences over the same calls.
+
+The library must be built in-tree first::
+
+    python -m paper_1805_12258_amd.build
+
+Importing this package raises ``ImportError`` when it is not.  torch is
+imported before the library is opened so that both use the same HIP runtime.
+"""
+import ctypes
+import os
+
+import torch
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libhs.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError("libhs.so is not built; run `python -m paper_1805_12258_amd.build` "
+                      "(there is no CPU fallback)")
+
+_lib = ctypes.CDLL(LIB_PATH)
+
+HS_OK = 0
+HS_ERR_INVALID = -1
+HS_ERR_OVERFLOW = -2
+HS_ERR_HIP = -3
+HS_ERR_UNSUPPORTED = -4
+HS_ERR_NOMEM = -5
+
+HS_DTYPE_F32, HS_DTYPE_F16, HS_DTYPE_BF16 = 0, 1, 2
+_DTYPES = {torch.float32: HS_DTYPE_F32, torch.float16: HS_DTYPE_F16, torch.bfloat16: HS_DTYPE_BF16}
+_DTYPE_NAMES = {"f32": HS_DTYPE_F32, "f16": HS_DTYPE_F16, "bf16": HS_DTYPE_BF16}
+
+
+class hs_cand(ctypes.Structure):
+    _fields_ = [("idx", ctypes.c_uint32), ("power", ctypes.c_float)]
+
+
+class hs_plan_desc(ctypes.Structure):
+    _fields_ = [("n_temp", ctypes.c_int64), ("n_chan", ctypes.c_int64), ("n_hp", ctypes.c_int32),
+                ("dtype", ctypes.c_int32), ("input_scale", ctypes.c_float),
+                ("n_fops", ctypes.c_int32), ("n_chans", ctypes.POINTER(ctypes.c_int64)),
+                ("tile_rows", ctypes.c_int32), ("persistent_blocks", ctypes.c_int32)]
+
+
+class hs_plan_info(ctypes.Structure):
+    _fields_ = [("n_temp", ctypes.c_int32), ("n_hp", ctypes.c_int32), ("dtype", ctypes.c_int32),
+                ("n_fops", ctypes.c_int32), ("n_chan_max", ctypes.c_int64),
+                ("s_row", ctypes.c_int32), ("s_k", ctypes.c_int32), ("s_bin", ctypes.c_int32),
+                ("tile_bins", ctypes.c_int32), ("tile_rows", ctypes.c_int32),
+                ("row_blocks", ctypes.c_int32), ("lds_bytes", ctypes.c_int32),
+                ("tiles_total", ctypes.c_int64), ("src_rows", ctypes.c_int32 * 17),
+                ("staged_words", ctypes.c_int64)]
+
+
+_P = ctypes.c_void_p
+_I64 = ctypes.c_int64
+_SIG = {
+    "hs_plan_create": ([ctypes.POINTER(_P), ctypes.POINTER(hs_plan_desc)], ctypes.c_int),
+    "hs_plan_destroy": ([_P], ctypes.c_int),
+    "hs_plan_info_get": ([_P, ctypes.POINTER(hs_plan_info)], ctypes.c_int),
+    "hs_sum": ([_P, _P, _I64, _P, _P], ctypes.c_int),
+    "hs_detect": ([_P, _P, _I64, _P, _P, _I64, _P, _P], ctypes.c_int),
+    "hs_detect_batched": ([_P, _P, _P, _P, _P, _P, _P, _P, _P], ctypes.c_int),
+    "hs_sort_workspace_bytes": ([_I64], ctypes.c_size_t),
+    "hs_sort_candidates": ([_P, _I64, _P, _P], ctypes.c_int),
+    "hs_backward_workspace_bytes": ([_P], ctypes.c_size_t),
+    "hs_sum_backward": ([_P, _P, _P, _P, _P], ctypes.c_int),
+    "hs_lse_workspace_bytes": ([_P], ctypes.c_size_t),
+    "hs_lse_forward": ([_P, _P, _I64, ctypes.c_float, _P, _P, _P], ctypes.c_int),
+    "hs_lse_backward": ([_P, _P, _I64, _P, ctypes.c_float, ctypes.c_float, _P, _P, _P],
+                        ctypes.c_int),
+    "hs_check_counts": ([ctypes.POINTER(ctypes.c_int64), ctypes.c_int32, _I64], ctypes.c_int),
+    "hs_status_string": ([ctypes.c_int], ctypes.c_char_p),
+    "hs_version": ([], ctypes.c_char_p),
+}
+for _name, (_args, _res) in _SIG.items():
+    _f = getattr(_lib, _name)
+    _f.argtypes = _args
+    _f.restype = _res
+    globals()["_c_" + _name] = _f
+
+
+class HsError(RuntimeError):
+    """A libhs call returned an error status."""
+
+    def __init__(self, status, what):
+        self.status = status
+        msg = _c_hs_status_string(status).decode()
+        super().__init__("%s failed: %s (%d)" % (what, msg, status))
+
+
+def _check(status, what):
+    if status != HS_OK:
+        raise HsError(status, what)
+
+
+def _stream(stream):
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _ptr(t):
+    return ctypes.c_void_p(0 if t is None else t.data_ptr())
+
+
+def _need_cuda(*ts):
+    for t in ts:
+        if t is not None and not t.is_cuda:
+            raise ValueError("libhs takes device tensors only")
+
+
+# --- C names --------------------------------------------------------------------
+
+def hs_plan_create(n_temp, n_chan=0, n_hp=8, dtype="f32", input_scale=1.0, n_chans=None,
+                   tile_rows=0, persistent_blocks=0):
+    """Create a plan (host only).  Returns an opaque handle (ctypes.c_void_p)."""
+    d = hs_plan_desc()
+    d.n_temp = int(n_temp)
+    d.n_chan = int(n_chan or 0)
+    d.n_hp = int(n_hp)
+    d.dtype = _DTYPE_NAMES[dtype] if isinstance(dtype, str) else _DTYPES.get(dtype, dtype)
+    d.input_scale = float(input_scale)
+    keep = None
+    if n_chans is not None:
+        keep = (ctypes.c_int64 * len(n_chans))(*[int(x) for x in n_chans])
+        d.n_fops = len(n_chans)
+        d.n_chans = ctypes.cast(keep, ctypes.POINTER(ctypes.c_int64))
+    d.tile_rows = int(tile_rows)
+    d.persistent_blocks = int(persistent_blocks)
+    h = ctypes.c_void_p()
+    _check(_c_hs_plan_create(ctypes.byref(h), ctypes.byref(d)), "hs_plan_create")
+    return h
+
+
+def hs_plan_destroy(handle):
+    _check(_c_hs_plan_destroy(handle), "hs_plan_destroy")
+
+
+def hs_plan_info_get(handle):
+    info = hs_plan_info()
+    _check(_c_hs_plan_info_get(handle, ctypes.byref(info)), "hs_plan_info_get")
+    out = {k: getattr(info, k) for k, _ in hs_plan_info._fields_}
+    out["src_rows"] = list(info.src_rows)
+    return out
+
+
+def hs_sum(handle, fop, ld, hp, stream=None):
+    _need_cuda(fop, hp)
+    _check(_c_hs_sum(handle, _ptr(fop), int(ld), _ptr(hp), _stream(stream)), "hs_sum")
+
+
+def hs_detect(handle, fop, ld, ta, out, capacity, counts, stream=None):
+    _need_cuda(fop, ta, out, counts)
+    _check(_c_hs_detect(handle, _ptr(fop), int(ld), _ptr(ta), _ptr(out), int(capacity),
+                        _ptr(counts), _stream(stream)), "hs_detect")
+
+
+def hs_detect_batched(handle, fops, lds, ta, out, out_offsets, caps, counts, stream=None):
+    _need_cuda(fops, lds, ta, out, out_offsets, caps, counts)
+    _check(_c_hs_detect_batched(handle, _ptr(fops), _ptr(lds), _ptr(ta), _ptr(out),
+                                _ptr(out_offsets), _ptr(caps), _ptr(counts), _stream(stream)),
+           "hs_detect_batched")
+
+
+def hs_sort_workspace_bytes(n):
+    return int(_c_hs_sort_workspace_bytes(int(n)))
+
+
+def hs_sort_candidates(cand, n, work, stream=None):
+    _need_cuda(cand, work)
+    _check(_c_hs_sort_candidates(_ptr(cand), int(n), _ptr(work), _stream(stream)),
+           "hs_sort_candidates")
+
+
+def hs_backward_workspace_bytes(handle):
+    return int(_c_hs_backward_workspace_bytes(handle))
+
+
+def hs_sum_backward(handle, g, dfop, work, stream=None):
+    _need_cuda(g, dfop, work)
+    _check(_c_hs_sum_backward(handle, _ptr(g), _ptr(dfop), _ptr(work), _stream(stream)),
+           "hs_sum_backward")
+
+
+def hs_lse_workspace_bytes(handle):
+    return int(_c_hs_lse_workspace_bytes(handle))
+
+
+def hs_lse_forward(handle, fop, ld, tau, lse, work, stream=None):
+    _need_cuda(fop, lse, work)
+    _check(_c_hs_lse_forward(handle, _ptr(fop), int(ld), float(tau), _ptr(lse), _ptr(work),
+                             _stream(stream)), "hs_lse_forward")
+
+
+def hs_lse_backward(handle, fop, ld, lse, tau, gscale, dfop, work, stream=None):
+    _need_cuda(fop, lse, dfop, work)
+    _check(_c_hs_lse_backward(handle, _ptr(fop), int(ld), _ptr(lse), float(tau), float(gscale),
+                              _ptr(dfop), _ptr(work), _stream(stream)), "hs_lse_backward")
+
+
+def hs_check_counts(counts_host, n_hp, capacity):
+    arr = (ctypes.c_int64 * (n_hp + 1))(*[int(x) for x in counts_host[:n_hp + 1]])
+    return _c_hs_check_counts(arr, int(n_hp), int(capacity))
+
+
+def hs_status_string(status):
+    return _c_hs_status_string(int(status)).decode()
+
+
+def hs_version():
+    return _c_hs_version().decode()
+
+
+# --- conveniences ------------------------------------------------------------------
+
+class Plan:
+    """Owning wrapper of an hs_plan handle."""
+
+    def __init__(self, n_temp, n_chan=0, n_hp=8, dtype="f32", input_scale=1.0, n_chans=None,
+                 tile_rows=0, persistent_blocks=0):
+        self.n_temp, self.n_hp = int(n_temp), int(n_hp)
+        self.n_chan = int(n_chan or 0)
+        self.n_chans = None if n_chans is None else [int(x) for x in n_chans]
+        if isinstance(dtype, str):
+            self.dtype = _DTYPE_NAMES[dtype]
+        else:
+            self.dtype = _DTYPES.get(dtype, dtype)
+        self.torch_dtype = {0: torch.float32, 1: torch.float16, 2: torch.bfloat16}.get(self.dtype)
+        self.input_scale = float(input_scale)
+        self.handle = hs_plan_create(n_temp, n_chan, n_hp, self.dtype, input_scale, n_chans,
+                                     tile_rows, persistent_blocks)
+        self.info = hs_plan_info_get(self.handle)
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h is not None and h.value:
+            _c_hs_plan_destroy(h)
+            self.handle = None
+
+    def _fop(self, fop):
+        if fop.dtype != self.torch_dtype or fop.dim() != 2 or fop.shape[0] != self.n_temp:
+            raise ValueError("FOP must be [n_temp][ld] of the plan's dtype")
+        if fop.stride(1) != 1:
+            raise ValueError("FOP rows must be contiguous")
+        return fop.stride(0)
+
+    def sum(self, fop, out=None, stream=None):
+        """All planes [H][T][N] fp32 (unscaled)."""
+        ld = self._fop(fop)
+        if out is None:
+            out = torch.empty((self.n_hp, self.n_temp, self.n_chan), dtype=torch.float32,
+                              device=fop.device)
+        hs_sum(self.handle, fop, ld, out, stream)
+        return out
+
+    def detect(self, fop, ta, capacity=None, out=None, counts=None, stream=None):
+        """Fused planes + detection.  Returns (out, counts) device tensors:
+        out is [capacity][2] int32 (word, power bits), counts [H+1] int64."""
+        ld = self._fop(fop)
+        dev = fop.device
+        if capacity is None:
+            capacity = out.shape[0] if out is not None else 1 << 20
+        if out is None:
+            out = torch.empty((max(int(capacity), 1), 2), dtype=torch.int32, device=dev)
+        if counts is None:
+            counts = torch.empty(self.n_hp + 1, dtype=torch.int64, device=dev)
+        hs_detect(self.handle, fop, ld, ta, out, capacity, counts, stream)
+        return out, counts
+
+
+def split_candidates(out, n):
+    """(word uint32 numpy, power float32 numpy) of the first n entries of `out`."""
+    import numpy as np
+    a = out[:n].cpu().numpy()
+    return a[:, 0].view(np.uint32).copy(), a[:, 1].view(np.float32).copy()

@@ -1,0 +1,350 @@
+// Host side of libhs: plan creation (shape checks, candidate-word widths,
+// tile geometry), argument validation and kernel dispatch.  Every entry point
+// returns an hs_status and catches C++ exceptions before they reach the ABI.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstring>
+#include <new>
+
+#include "hs_internal.h"
+
+namespace {
+
+int ceil_log2(int64_t x)
+{
+    int s = 0;
+    while (((int64_t)1 << s) < x) ++s;
+    return s;
+}
+
+bool is_pow2_scale(float s)
+{
+    if (!(s > 0.0f) || !std::isfinite(s)) return false;
+    int e = 0;
+    return std::frexp(s, &e) == 0.5f;
+}
+
+int elem_bytes(int dtype) { return dtype == HS_DTYPE_F32 ? 4 : 2; }
+int ld_align(int dtype) { return dtype == HS_DTYPE_F32 ? 4 : 8; }
+
+// Largest LDS footprint the planner gives one block, so that two blocks fit
+// in the 160 KiB of a gfx950 compute unit.
+constexpr int kLdsBudget = 78 * 1024;
+
+hs_status from_hip(hipError_t e) { return e == hipSuccess ? HS_OK : HS_ERR_HIP; }
+
+bool fop_ok(const hs_plan* p, const void* fop, int64_t ld, int64_t N)
+{
+    if (!fop || ld < N) return false;
+    if (reinterpret_cast<uintptr_t>(fop) & 15) return false;
+    return ld % ld_align(p->dtype) == 0;
+}
+
+hsk::TileArgs tile_args(const hs_plan* p, const void* fop, int64_t ld)
+{
+    hsk::TileArgs a{};
+    a.fop = fop;
+    a.ld = ld;
+    a.N = p->N;
+    a.T = (int32_t)p->T;
+    a.c = (int32_t)(p->T / 2);
+    a.R = p->tile_rows;
+    a.row_blocks = p->row_blocks;
+    a.scale = p->scale;
+    a.inv_scale = 1.0f / p->scale;
+    a.s_row = p->s_row;
+    a.s_bin = p->s_bin;
+    return a;
+}
+
+int64_t bin_tiles(int64_t n) { return (n + hsk::kTileBins - 1) / hsk::kTileBins; }
+
+}  // namespace
+
+extern "C" {
+
+hs_status hs_plan_create(hs_plan** out, const hs_plan_desc* d)
+{
+    if (!out || !d) return HS_ERR_INVALID;
+    *out = nullptr;
+    try {
+        if (d->n_temp < 1 || d->n_temp > (1 << 20)) return HS_ERR_INVALID;
+        if (d->n_hp < 1 || d->n_hp > hsk::kMaxH) return HS_ERR_INVALID;
+        if (d->dtype != HS_DTYPE_F32 && d->dtype != HS_DTYPE_F16 && d->dtype != HS_DTYPE_BF16)
+            return HS_ERR_INVALID;
+        const float scale = d->input_scale == 0.0f ? 1.0f : d->input_scale;
+        if (!is_pow2_scale(scale)) return HS_ERR_INVALID;
+        if (d->n_fops < 0) return HS_ERR_INVALID;
+        if (d->tile_rows < 0 || d->persistent_blocks < 0) return HS_ERR_INVALID;
+
+        hs_plan* p = new hs_plan();
+        p->T = d->n_temp;
+        p->H = d->n_hp;
+        p->dtype = d->dtype;
+        p->scale = scale;
+        p->n_fops = d->n_fops;
+        p->persistent_blocks = d->persistent_blocks;
+        int64_t nmax = 0;
+        if (d->n_fops == 0) {
+            if (d->n_chan < 1 || d->n_chan > INT32_MAX) { delete p; return HS_ERR_INVALID; }
+            nmax = d->n_chan;
+        } else {
+            if (!d->n_chans) { delete p; return HS_ERR_INVALID; }
+            p->n_chans.assign(d->n_chans, d->n_chans + d->n_fops);
+            for (int64_t n : p->n_chans) {
+                if (n < 1 || n > INT32_MAX) { delete p; return HS_ERR_INVALID; }
+                if (n > nmax) nmax = n;
+            }
+        }
+        p->N = nmax;
+        p->s_bin = ceil_log2(nmax);
+        p->s_k = ceil_log2(p->H);
+        const int s_r = ceil_log2(p->T);
+        if (p->s_bin + p->s_k + s_r > 32) { delete p; return HS_ERR_INVALID; }
+        p->s_row = p->s_bin + p->s_k;
+
+        // Rows per tile: the whole column when the staged ranges fit the LDS
+        // budget, else the largest row block that does.
+        int R = d->tile_rows > 0 ? (int)std::min<int64_t>(d->tile_rows, p->T) : (int)p->T;
+        if (d->tile_rows == 0) {
+            // the staged region is addressed by LDS-DMA through M0: keep it
+            // below 64 KiB
+            while (R > 1 && (hsk::fused_lds_bytes((int)p->T, R, p->H, hsk::kModeDetect) > kLdsBudget ||
+                             hsk::fused_stage_words((int)p->T, R, p->H) * 4 > 65536))
+                R = (R + 1) / 2;
+        }
+        p->tile_rows = R;
+        p->row_blocks = (int)((p->T + R - 1) / R);
+        p->lds_bytes = hsk::fused_lds_bytes((int)p->T, R, p->H, hsk::kModeDetect);
+        if (p->lds_bytes > 160 * 1024 ||
+            hsk::fused_stage_words((int)p->T, R, p->H) * 4 > 65536) {
+            delete p;
+            return HS_ERR_UNSUPPORTED;
+        }
+
+        if (d->n_fops == 0) {
+            p->tiles_total = p->row_blocks * bin_tiles(p->N);
+        } else {
+            p->tile_prefix.resize(d->n_fops + 1);
+            int64_t acc = 0;
+            for (int f = 0; f < d->n_fops; ++f) {
+                p->tile_prefix[f] = acc;
+                acc += p->row_blocks * bin_tiles(p->n_chans[f]);
+            }
+            p->tile_prefix[d->n_fops] = acc;
+            p->tiles_total = acc;
+        }
+        *out = p;
+        return HS_OK;
+    } catch (const std::bad_alloc&) {
+        return HS_ERR_NOMEM;
+    } catch (...) {
+        return HS_ERR_INVALID;
+    }
+}
+
+hs_status hs_plan_destroy(hs_plan* p)
+{
+    if (!p) return HS_OK;
+    int cur = -1;
+    bool have_dev = hipGetDevice(&cur) == hipSuccess;
+    for (int dev = 0; dev < 64; ++dev) {
+        if (p->d_tables[dev]) {
+            if (have_dev) hipSetDevice(dev);
+            hipFree(p->d_tables[dev]);
+        }
+    }
+    if (have_dev && cur >= 0) hipSetDevice(cur);
+    delete p;
+    return HS_OK;
+}
+
+hs_status hs_plan_info_get(const hs_plan* p, hs_plan_info* info)
+{
+    if (!p || !info) return HS_ERR_INVALID;
+    std::memset(info, 0, sizeof(*info));
+    info->n_temp = (int32_t)p->T;
+    info->n_hp = p->H;
+    info->dtype = p->dtype;
+    info->n_fops = p->n_fops;
+    info->n_chan_max = p->N;
+    info->s_row = p->s_row;
+    info->s_k = p->s_k;
+    info->s_bin = p->s_bin;
+    info->tile_bins = hsk::kTileBins;
+    info->tile_rows = p->tile_rows;
+    info->row_blocks = p->row_blocks;
+    info->lds_bytes = p->lds_bytes;
+    info->tiles_total = p->tiles_total;
+    // distinct source rows of each stretch factor over the full column, and the
+    // words one full-height tile at a 256-bin aligned position stages
+    const int64_t c = p->T / 2;
+    int64_t staged = 0;
+    for (int m = 1; m <= p->H; ++m) {
+        const int64_t rows = hsk::floordiv(p->T - 1 - c, m) - hsk::floordiv(-c, m) + 1;
+        info->src_rows[m] = (int32_t)rows;
+        if (m >= 2) staged += rows * ((hsk::kTileBins - 1) / m + 1);
+    }
+    info->staged_words = staged;
+    return HS_OK;
+}
+
+hs_status hs_sum(const hs_plan* p, const void* fop, int64_t ld, float* hp, void* stream)
+{
+    if (!p || !hp || p->n_fops != 0) return HS_ERR_INVALID;
+    if (!fop_ok(p, fop, ld, p->N)) return HS_ERR_INVALID;
+    try {
+        hsk::TileArgs a = tile_args(p, fop, ld);
+        a.hp = hp;
+        return from_hip(hsk::launch_fused(hsk::kModeSum, p->dtype, p->H, a, p->tiles_total,
+                                          p->lds_bytes, (hipStream_t)stream));
+    } catch (...) {
+        return HS_ERR_HIP;
+    }
+}
+
+hs_status hs_detect(const hs_plan* p, const void* fop, int64_t ld, const float* ta, hs_cand* out,
+                    int64_t capacity, int64_t* counts, void* stream)
+{
+    if (!p || p->n_fops != 0 || !ta || !counts || capacity < 0) return HS_ERR_INVALID;
+    if (capacity > 0 && !out) return HS_ERR_INVALID;
+    if (!fop_ok(p, fop, ld, p->N)) return HS_ERR_INVALID;
+    try {
+        hipStream_t s = (hipStream_t)stream;
+        hipError_t e = hsk::launch_zero_i64(counts, p->H + 1, s);
+        if (e != hipSuccess) return HS_ERR_HIP;
+        hsk::TileArgs a = tile_args(p, fop, ld);
+        a.ta = ta;
+        a.out = out;
+        a.cap = capacity;
+        a.counts = reinterpret_cast<unsigned long long*>(counts);
+        return from_hip(hsk::launch_fused(hsk::kModeDetect, p->dtype, p->H, a, p->tiles_total,
+                                          p->lds_bytes, s));
+    } catch (...) {
+        return HS_ERR_HIP;
+    }
+}
+
+hs_status hs_detect_batched(const hs_plan* p, const void* const* fops, const int64_t* lds,
+                            const float* ta, hs_cand* out, const int64_t* out_offsets,
+                            const int64_t* caps, int64_t* counts, void* stream)
+{
+    if (!p || p->n_fops < 1 || !fops || !lds || !ta || !out || !out_offsets || !caps || !counts)
+        return HS_ERR_INVALID;
+    try {
+        int dev = 0;
+        if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return HS_ERR_HIP;
+        int64_t* tables = nullptr;
+        {
+            std::lock_guard<std::mutex> g(p->mu);
+            if (!p->d_tables[dev]) {
+                const size_t n = (size_t)p->n_fops * 2 + 1;
+                std::vector<int64_t> h(n);
+                for (int f = 0; f < p->n_fops; ++f) h[f] = p->n_chans[f];
+                for (int f = 0; f <= p->n_fops; ++f) h[p->n_fops + f] = p->tile_prefix[f];
+                int64_t* d = nullptr;
+                if (hipMalloc(&d, n * sizeof(int64_t)) != hipSuccess) return HS_ERR_NOMEM;
+                if (hipMemcpy(d, h.data(), n * sizeof(int64_t), hipMemcpyHostToDevice) != hipSuccess) {
+                    hipFree(d);
+                    return HS_ERR_HIP;
+                }
+                p->d_tables[dev] = d;
+            }
+            tables = p->d_tables[dev];
+        }
+        hipStream_t s = (hipStream_t)stream;
+        hipError_t e = hsk::launch_zero_i64(counts, (int64_t)p->n_fops * (p->H + 1), s);
+        if (e != hipSuccess) return HS_ERR_HIP;
+        hsk::BatchArgs b{};
+        b.fops = fops;
+        b.lds = lds;
+        b.n_chans = tables;
+        b.tile_prefix = tables + p->n_fops;
+        b.tiles_total = p->tiles_total;
+        b.n_fops = p->n_fops;
+        b.T = (int32_t)p->T;
+        b.c = (int32_t)(p->T / 2);
+        b.R = p->tile_rows;
+        b.row_blocks = p->row_blocks;
+        b.scale = p->scale;
+        b.inv_scale = 1.0f / p->scale;
+        b.ta = ta;
+        b.out = out;
+        b.out_offsets = out_offsets;
+        b.caps = caps;
+        b.counts = reinterpret_cast<unsigned long long*>(counts);
+        b.s_row = p->s_row;
+        b.s_bin = p->s_bin;
+        int grid = p->persistent_blocks;
+        if (grid == 0) {
+            hipDeviceProp_t prop;
+            if (hipGetDeviceProperties(&prop, dev) != hipSuccess) return HS_ERR_HIP;
+            int per_cu = (160 * 1024) / p->lds_bytes;
+            if (per_cu > 4) per_cu = 4;
+            if (per_cu < 1) per_cu = 1;
+            grid = prop.multiProcessorCount * per_cu;
+        }
+        if ((int64_t)grid > p->tiles_total) grid = (int)p->tiles_total;
+        return from_hip(hsk::launch_batched(p->dtype, p->H, b, grid, p->lds_bytes, s));
+    } catch (...) {
+        return HS_ERR_HIP;
+    }
+}
+
+size_t hs_sort_workspace_bytes(int64_t n) { return n > 0 ? (size_t)n * 16 + 4096 : 0; }
+
+hs_status hs_sort_candidates(hs_cand* cand, int64_t n, void* work, void* stream)
+{
+    (void)cand; (void)n; (void)work; (void)stream;
+    return HS_ERR_UNSUPPORTED;
+}
+
+size_t hs_backward_workspace_bytes(const hs_plan* p) { (void)p; return 0; }
+
+hs_status hs_sum_backward(const hs_plan* p, const float* g, float* dfop, void* work, void* stream)
+{
+    (void)p; (void)g; (void)dfop; (void)work; (void)stream;
+    return HS_ERR_UNSUPPORTED;
+}
+
+size_t hs_lse_workspace_bytes(const hs_plan* p) { (void)p; return 0; }
+
+hs_status hs_lse_forward(const hs_plan* p, const void* fop, int64_t ld, float tau, float* lse,
+                         void* work, void* stream)
+{
+    (void)p; (void)fop; (void)ld; (void)tau; (void)lse; (void)work; (void)stream;
+    return HS_ERR_UNSUPPORTED;
+}
+
+hs_status hs_lse_backward(const hs_plan* p, const void* fop, int64_t ld, const float* lse,
+                          float tau, float gscale, float* dfop, void* work, void* stream)
+{
+    (void)p; (void)fop; (void)ld; (void)lse; (void)tau; (void)gscale; (void)dfop; (void)work;
+    (void)stream;
+    return HS_ERR_UNSUPPORTED;
+}
+
+hs_status hs_check_counts(const int64_t* counts_host, int32_t n_hp, int64_t capacity)
+{
+    if (!counts_host || n_hp < 1 || n_hp > hsk::kMaxH || capacity < 0) return HS_ERR_INVALID;
+    if (counts_host[n_hp] < 0) return HS_ERR_INVALID;
+    return counts_host[n_hp] > capacity ? HS_ERR_OVERFLOW : HS_OK;
+}
+
+const char* hs_status_string(hs_status s)
+{
+    switch (s) {
+    case HS_OK: return "ok";
+    case HS_ERR_INVALID: return "invalid argument";
+    case HS_ERR_OVERFLOW: return "candidate list exceeds capacity";
+    case HS_ERR_HIP: return "HIP runtime error";
+    case HS_ERR_UNSUPPORTED: return "unsupported";
+    case HS_ERR_NOMEM: return "out of memory";
+    }
+    return "unknown status";
+}
+
+const char* hs_version(void) { return "hs-mi355x 0.1.0 (gfx950)"; }
+
+}  // extern "C"

@@ -1,0 +1,119 @@
+// Internal declarations of libhs: plan object, tile geometry, launchers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <mutex>
+#include <vector>
+
+#include "hs.h"
+
+namespace hsk {
+
+// Tile geometry of the fused kernels.  A tile is a block of template rows
+// times kTileBins consecutive bins; each lane owns kV consecutive bins of one
+// row at a time, a wave sweeps one row of the tile per step.
+constexpr int kLanes = 64;
+constexpr int kV = 4;
+constexpr int kTileBins = kV * kLanes;   // 256
+constexpr int kWaves = 8;
+constexpr int kThreads = kWaves * kLanes;
+constexpr int kCandCap = 512;            // LDS candidate buffer entries per block
+constexpr int kMaxH = 16;
+
+// Words reserved per staged source row of stretch factor m: the largest
+// number of distinct floor(j/m) over kTileBins consecutive bins, rounded up
+// to 4 words so every row starts 16-byte aligned.
+__host__ __device__ constexpr int stage_pitch(int m)
+{
+    return (((kTileBins + m - 2) / m + 1) + 3) & ~3;
+}
+
+// LDS bytes after the staged region: thresholds [R][H], the candidate buffer,
+// its global base slot and the per-plane counters.
+__host__ __device__ constexpr int smem_tail_bytes(int R, int H)
+{
+    return ((R * H + 3) & ~3) * 4 + kCandCap * 8 + 8 + (kMaxH + 1) * 4;
+}
+
+__host__ __device__ inline int64_t floordiv(int64_t a, int64_t b)
+{
+    int64_t q = a / b;
+    return (q * b > a) ? q - 1 : q;
+}
+
+// Arguments of one fused launch over one FOP (or one FOP of a batch).
+struct TileArgs {
+    const void* fop;
+    int64_t ld;
+    int64_t N;              // bins
+    int32_t T;              // rows
+    int32_t c;              // centre row: row r holds template index r - c
+    int32_t R;              // rows per tile
+    int32_t row_blocks;     // tiles across the rows
+    float scale;            // stored = power * scale
+    float inv_scale;
+    const float* ta;        // [H][T]
+    // detect
+    hs_cand* out;
+    int64_t cap;
+    unsigned long long* counts;   // [H+1]
+    int32_t s_row, s_bin;
+    // materialised planes
+    float* hp;              // [H][T][N]
+};
+
+// Arguments of the batched persistent launch.
+struct BatchArgs {
+    const void* const* fops;
+    const int64_t* lds;
+    const int64_t* n_chans;       // device [n_fops]
+    const int64_t* tile_prefix;   // device [n_fops + 1]
+    int64_t tiles_total;
+    int32_t n_fops;
+    int32_t T, c, R, row_blocks;
+    float scale, inv_scale;
+    const float* ta;
+    hs_cand* out;
+    const int64_t* out_offsets;
+    const int64_t* caps;
+    unsigned long long* counts;   // [n_fops][H+1]
+    int32_t s_row, s_bin;
+};
+
+enum Mode { kModeDetect = 0, kModeSum = 1 };
+
+// LDS bytes of the fused kernel for a tile of `rows` rows starting at every
+// admissible row offset (maximum over the row blocks of the plan).
+int fused_lds_bytes(int T, int R, int H, int mode);
+// Words of the staged source region alone (largest over the row blocks).
+int fused_stage_words(int T, int R, int H);
+
+hipError_t launch_fused(int mode, int dtype, int H, const TileArgs& a, int64_t n_tiles,
+                        int lds_bytes, hipStream_t s);
+hipError_t launch_batched(int dtype, int H, const BatchArgs& a, int grid, int lds_bytes,
+                          hipStream_t s);
+hipError_t launch_zero_i64(int64_t* p, int64_t n, hipStream_t s);
+
+}  // namespace hsk
+
+struct hs_plan {
+    int64_t T = 0;
+    int64_t N = 0;          // single FOP: bins; batched: maximum bins
+    int H = 0;
+    int dtype = 0;
+    float scale = 1.0f;
+    int n_fops = 0;
+    std::vector<int64_t> n_chans;
+    int s_row = 0, s_k = 0, s_bin = 0;
+    int tile_rows = 0, row_blocks = 0;
+    int lds_bytes = 0;
+    int64_t tiles_total = 0;
+    int persistent_blocks = 0;
+    std::vector<int64_t> tile_prefix;   // batched: tiles before each FOP
+
+    // Device copies of the batched tables, made on first use per device.
+    mutable std::mutex mu;
+    mutable int64_t* d_tables[64] = {nullptr};
+};

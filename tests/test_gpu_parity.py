@@ -1,0 +1,138 @@
+"""GPU parity: libhs (through the C ABI) against the CPU oracle.
+
+Planes must be bitwise equal to the fp32 oracle (same sum order, Eq. 2) and
+candidate lists equal as sets of (word, power bits) after sorting by word,
+with exact per-plane counts.  Inputs are seeded; padding columns beyond the
+last bin hold NaN so a read outside the plane cannot go unnoticed.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_1805_12258_amd as hs
+import synth
+from tests.helpers import (assert_same_candidates, gpu_detect, oracle_detect_sorted,
+                           padded_device, random_thresholds)
+
+pytestmark = pytest.mark.gpu
+
+SHAPES = [
+    (1, 1, 1), (1, 300, 16), (5, 64, 8), (9, 257, 3), (21, 1000, 13), (64, 4097, 16),
+    (85, 5000, 8), (127, 777, 5), (2, 513, 2), (85, 256 * 7 + 3, 16),
+]
+
+
+def exp_plane(T, N, seed):
+    return synth.noise(T, N, seed)
+
+
+@pytest.mark.parametrize("T,N,H", SHAPES)
+def test_sum_bitwise(T, N, H):
+    print("case", T, N, H, flush=True)
+    x = exp_plane(T, N, 100 + T + N + H)
+    dev, store = padded_device(x)
+    plan = hs.Plan(T, N, H)
+    hp = plan.sum(dev).cpu().numpy()
+    ref = oracle.sum_f32(store.numpy(), H)
+    assert np.array_equal(hp.view(np.uint32), ref.view(np.uint32))
+
+
+@pytest.mark.parametrize("T,N,H", SHAPES)
+def test_detect_bitwise(T, N, H):
+    print("case", T, N, H, flush=True)
+    x = exp_plane(T, N, 200 + T + N + H)
+    ta = random_thresholds(H, T, T * N + H)
+    dev, store = padded_device(x)
+    plan = hs.Plan(T, N, H)
+    got = gpu_detect(plan, dev, ta, capacity=H * T * N + 16)
+    want = oracle_detect_sorted(store, H, ta)
+    assert_same_candidates(got, want)
+
+
+@pytest.mark.parametrize("T,N,H,rows", [(21, 3000, 8, 4), (64, 1000, 16, 7), (85, 2000, 8, 30)])
+def test_row_blocked_tiles(T, N, H, rows):
+    print("case", T, N, H, rows, flush=True)
+    x = exp_plane(T, N, 300 + rows)
+    ta = random_thresholds(H, T, rows)
+    dev, store = padded_device(x)
+    plan = hs.Plan(T, N, H, tile_rows=rows)
+    assert plan.info["row_blocks"] == (T + rows - 1) // rows
+    got = gpu_detect(plan, dev, ta, capacity=H * T * N)
+    assert_same_candidates(got, oracle_detect_sorted(store, H, ta))
+    hp = plan.sum(dev).cpu().numpy()
+    assert np.array_equal(hp.view(np.uint32), oracle.sum_f32(store.numpy(), H).view(np.uint32))
+
+
+def test_every_point_a_candidate():
+    """Thresholds of -inf: every point of every plane is a candidate, which
+    overflows each block's LDS buffer and exercises the spill path."""
+    T, N, H = 21, 3000, 8
+    x = exp_plane(T, N, 7)
+    ta = np.full((H, T), -np.inf, dtype=np.float32)
+    dev, store = padded_device(x)
+    plan = hs.Plan(T, N, H)
+    got = gpu_detect(plan, dev, ta, capacity=H * T * N)
+    assert got[2][-1] == H * T * N
+    assert_same_candidates(got, oracle_detect_sorted(store, H, ta))
+
+
+def test_capacity_overflow_counts_exact():
+    T, N, H = 21, 5000, 8
+    x = exp_plane(T, N, 8)
+    ta = synth.thresholds(H, T)
+    dev, store = padded_device(x)
+    plan = hs.Plan(T, N, H)
+    wi, wp, wc = oracle_detect_sorted(store, H, ta)
+    cap = 10
+    gi, gp, gc = gpu_detect(plan, dev, ta, capacity=cap)
+    assert np.array_equal(gc, wc)
+    assert len(gi) == cap
+    pos = np.searchsorted(wi, gi)
+    assert np.all(wi[pos] == gi) and np.array_equal(wp[pos].view(np.uint32), gp.view(np.uint32))
+    assert hs.hs_check_counts(gc, H, cap) == hs.HS_ERR_OVERFLOW
+    assert hs.hs_check_counts(gc, H, int(gc[-1])) == hs.HS_OK
+
+
+def test_tiny_workload():
+    """The tiny configuration: 21 x 2^16, 8 planes, T_k = k + 6 sqrt(k)."""
+    x = synth.make_tiny()
+    H, T = 8, x.shape[0]
+    ta = synth.thresholds(H, T)
+    dev, store = padded_device(x, pad=0)
+    plan = hs.Plan(T, x.shape[1], H)
+    got = gpu_detect(plan, dev, ta)
+    assert_same_candidates(got, oracle_detect_sorted(store, H, ta))
+    hp = plan.sum(dev).cpu().numpy()
+    assert np.array_equal(hp.view(np.uint32), oracle.sum_f32(store.numpy(), H).view(np.uint32))
+
+
+@pytest.mark.parametrize("dtype", [torch.float16, torch.bfloat16])
+@pytest.mark.parametrize("T,N,H", [(21, 1 << 16, 8), (9, 1001, 16), (85, 3000, 8)])
+def test_reduced_precision_bitwise(dtype, T, N, H):
+    """fp16/bf16 storage of x/8: the kernel converts exactly and sums in fp32,
+    so its planes and candidates equal the fp32 oracle run on the stored
+    values (converted to fp32) with the same scale."""
+    print("case", dtype, T, N, H, flush=True)
+    x = synth.make_tiny() if (T, N) == (21, 1 << 16) else exp_plane(T, N, 400 + N)
+    ta = synth.thresholds(H, T)
+    scale = 0.125
+    dev, store = padded_device(x, dtype=dtype, scale=scale)
+    name = "f16" if dtype == torch.float16 else "bf16"
+    plan = hs.Plan(T, N, H, dtype=name, input_scale=scale)
+    got = gpu_detect(plan, dev, ta)
+    assert_same_candidates(got, oracle_detect_sorted(store, H, ta, scale=scale))
+    hp = plan.sum(dev).cpu().numpy()
+    ref = oracle.sum_f32(store.to(torch.float32).numpy(), H) / np.float32(scale)
+    assert np.array_equal(hp.view(np.uint32), ref.view(np.uint32))
+
+
+def test_repeat_calls_deterministic_sets():
+    T, N, H = 85, 20000, 8
+    x = exp_plane(T, N, 9)
+    ta = synth.thresholds(H, T)
+    dev, _ = padded_device(x)
+    plan = hs.Plan(T, N, H)
+    a = gpu_detect(plan, dev, ta)
+    b = gpu_detect(plan, dev, ta)
+    assert_same_candidates(a, (np.sort(b[0]), b[1][np.argsort(b[0])], b[2]))

@@ -1,0 +1,123 @@
+"""Host-side checks of libhs.so: no GPU needed, no compute launched.
+
+The library loads, exports every entry point include/hs.h declares, its
+planner reproduces the staging counts of Sec. IV-C, and its argument
+validation rejects bad shapes before anything reaches a GPU.
+"""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import paper_1805_12258_amd as hs
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    txt = open(os.path.join(ROOT, "include", "hs.h")).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(hs_[a-z_0-9]+)\s*\(", txt)))
+
+
+def test_exports_every_declared_symbol():
+    names = declared_functions()
+    assert len(names) >= 15
+    lib = ctypes.CDLL(hs.LIB_PATH)
+    for n in names:
+        assert hasattr(lib, n), n
+
+
+def test_single_hip_runtime_in_process():
+    maps = open("/proc/self/maps").read()
+    libs = set(re.findall(r"\S*libamdhip64\S*", maps))
+    assert len(libs) == 1, libs
+
+
+def test_version_and_status_strings():
+    assert "gfx950" in hs.hs_version()
+    assert hs.hs_status_string(hs.HS_ERR_OVERFLOW) == "candidate list exceeds capacity"
+    assert hs.hs_status_string(0) == "ok"
+
+
+def test_plan_ska_geometry():
+    """85 templates, 8 planes: distinct source rows per stretch factor are
+    85, 43, 29, 22, 18, 15, 13, 12 (237 in all, under the bound 240 of Sec. IV-C)."""
+    p = hs.Plan(85, 1 << 21, 8)
+    info = p.info
+    assert info["src_rows"][1:9] == [85, 43, 29, 22, 18, 15, 13, 12]
+    assert sum(info["src_rows"][1:9]) == 237
+    assert (info["s_row"], info["s_k"], info["s_bin"]) == (24, 3, 21)
+    assert info["tile_rows"] == 85 and info["row_blocks"] == 1
+    assert info["tiles_total"] == (1 << 21) // info["tile_bins"]
+    # staged words per full tile ~ sum_m rows_m * B/m: 0.54x of the tile's own points
+    ratio = info["staged_words"] / (85 * info["tile_bins"])
+    assert 0.53 < ratio < 0.56
+
+
+def test_plan_h16_packing():
+    p = hs.Plan(85, 1 << 21, 16)
+    assert (p.info["s_row"], p.info["s_k"], p.info["s_bin"]) == (25, 4, 21)
+
+
+def test_plan_row_blocks_for_tall_planes():
+    p = hs.Plan(2001, 1 << 12, 16)
+    info = p.info
+    assert info["row_blocks"] > 1
+    assert info["lds_bytes"] <= 80 * 1024
+    assert info["tile_rows"] * info["row_blocks"] >= 2001
+
+
+def test_plan_batched_tiles():
+    lens = [1 << 19, 1 << 20, 1 << 21, 1000, 1]
+    p = hs.Plan(85, 0, 16, n_chans=lens)
+    tb = p.info["tile_bins"]
+    assert p.info["tiles_total"] == sum((n + tb - 1) // tb for n in lens)
+    assert p.info["n_chan_max"] == 1 << 21
+
+
+@pytest.mark.parametrize("kw", [
+    dict(n_temp=0, n_chan=10, n_hp=8),
+    dict(n_temp=85, n_chan=0, n_hp=8),
+    dict(n_temp=85, n_chan=10, n_hp=0),
+    dict(n_temp=85, n_chan=10, n_hp=17),
+    dict(n_temp=85, n_chan=10, n_hp=8, input_scale=0.1),
+    dict(n_temp=85, n_chan=10, n_hp=8, input_scale=-0.5),
+    dict(n_temp=255, n_chan=1 << 22, n_hp=16),        # 8 + 4 + 22 bits > 32
+    dict(n_temp=85, n_chan=0, n_hp=8, n_chans=[10, 0]),
+    dict(n_temp=85, n_chan=10, n_hp=8, dtype=7),
+])
+def test_plan_rejects_bad_shapes(kw):
+    with pytest.raises(hs.HsError) as e:
+        hs.Plan(**kw)
+    assert e.value.status == hs.HS_ERR_INVALID
+
+
+def test_plan_accepts_limits():
+    hs.Plan(1, 1, 1)
+    hs.Plan(128, 1 << 21, 16)                   # 7 + 4 + 21 = 32 bits
+    hs.Plan(85, 1 << 21, 8, dtype="bf16", input_scale=0.125)
+
+
+def test_check_counts():
+    assert hs.hs_check_counts([1, 2, 3], 2, 3) == hs.HS_OK
+    assert hs.hs_check_counts([1, 2, 4], 2, 3) == hs.HS_ERR_OVERFLOW
+    assert hs.hs_check_counts([0, 0, -1], 2, 3) == hs.HS_ERR_INVALID
+
+
+def test_null_arguments_rejected_without_gpu():
+    p = hs.Plan(21, 1000, 8)
+    null = ctypes.c_void_p(0)
+    assert hs._c_hs_detect(p.handle, null, 1000, null, null, 0, null, null) == hs.HS_ERR_INVALID
+    assert hs._c_hs_sum(p.handle, null, 1000, null, null) == hs.HS_ERR_INVALID
+    # misaligned FOP pointer and bad leading dimension are rejected on the host
+    fake = ctypes.c_void_p(0x1000 + 4)
+    out = ctypes.c_void_p(0x2000)
+    assert hs._c_hs_sum(p.handle, fake, 1000, out, null) == hs.HS_ERR_INVALID
+    assert hs._c_hs_sum(p.handle, ctypes.c_void_p(0x1000), 1002, out, null) == hs.HS_ERR_INVALID
+    assert hs._c_hs_sum(p.handle, ctypes.c_void_p(0x1000), 996, out, null) == hs.HS_ERR_INVALID
+    pb = hs.Plan(21, 0, 8, n_chans=[100, 200])
+    assert hs._c_hs_detect(pb.handle, ctypes.c_void_p(0x1000), 1000, out, out, 1, out,
+                           null) == hs.HS_ERR_INVALID
