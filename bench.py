@@ -1,0 +1,206 @@
+"""Benchmark: fused harmonic summing + detection on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-variants]
+                    [--batched N_FOPS] [--copy-calibration]
+
+Workload: one filter-output plane of 85 templates x 2^21 bins of fp32 power
+(Exp(1) noise, 50 injected harmonic signals, seed 2), 8 harmonic planes,
+thresholds T_k = k + 6 sqrt(k), full candidate list.  A step is one
+hs_detect call (counter clear + fused kernel) over the plane, which is
+resident in HBM before the timed region starts.
+
+Prints one JSON line.  `value` is FOP points per second (every point taken
+through all 8 planes and the threshold test).  `roofline` refers to the fused
+kernel: algorithmic bytes (one read of the FOP + 8 bytes per candidate + the
+counters) over its average launch time, measured with HIP events on the
+launch stream.  `traffic` comes from rocprofv3 FETCH_SIZE / WRITE_SIZE
+counters recorded in profiles/ for the current kernel sources (null when the
+sources changed since).  `cpu_baseline` times the CPU oracle on a bounded
+sample of the same plane.
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+import torch
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+KERNEL_SOURCES = ["paper_1805_12258_amd/csrc/hs_fused_impl.h",
+                  "paper_1805_12258_amd/csrc/hs_fused_f32.hip",
+                  "paper_1805_12258_amd/csrc/hs_internal.h"]
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "ska_detect_f32_traffic.json")
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        h.update(open(os.path.join(ROOT, f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def stored_traffic():
+    """Per-launch HBM bytes of the fused kernel from the committed counter
+    summary, or None when it was taken on different kernel sources."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    d = json.load(open(TRAFFIC_FILE))
+    if d.get("source_hash") != kernel_source_hash():
+        return None
+    return d
+
+
+def time_detect(plan, fop, ta, capacity, steps, warmup):
+    import paper_1805_12258_amd as hs
+    dev = fop.device
+    out = torch.empty((capacity, 2), dtype=torch.int32, device=dev)
+    counts = torch.empty(plan.n_hp + 1, dtype=torch.int64, device=dev)
+    ld = fop.stride(0)
+    for _ in range(warmup):
+        hs.hs_detect(plan.handle, fop, ld, ta, out, capacity, counts)
+    torch.cuda.synchronize()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+          for _ in range(steps)]
+    t0 = torch.cuda.Event(enable_timing=True)
+    t1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    wall0 = time.perf_counter()
+    t0.record()
+    for i in range(steps):
+        ev[i][0].record()
+        hs.hs_detect(plan.handle, fop, ld, ta, out, capacity, counts)
+        ev[i][1].record()
+    t1.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - wall0
+    total_ms = t0.elapsed_time(t1)
+    per_launch = [a.elapsed_time(b) for a, b in ev]
+    return dict(ms_per_step=total_ms / steps, launch_ms=float(np.mean(per_launch)),
+                launch_ms_min=float(np.min(per_launch)), wall_s=wall,
+                counts=counts.cpu().numpy().tolist())
+
+
+def cpu_baseline(fop_cpu, H, ta_np, max_bins):
+    """The oracle (Algorithm 1 order, fp32, with detection) on the first
+    `max_bins` bins of the plane: a prefix of bins is self-contained, since
+    every source bin floor(j/m) <= j."""
+    import oracle
+    sample = np.ascontiguousarray(fop_cpu[:, :max_bins].numpy())
+    threads = len(os.sched_getaffinity(0))
+    threads = min(threads, 16)
+    cap = 1 << 22
+    oracle.detect_f32(sample[:, :1024], H, ta_np, cap=cap, nthreads=threads)     # load + warm
+    t = time.perf_counter()
+    oracle.detect_f32(sample, H, ta_np, cap=cap, nthreads=threads)
+    dt = time.perf_counter() - t
+    pts = sample.shape[0] * sample.shape[1]
+    t1 = time.perf_counter()
+    one = np.ascontiguousarray(sample[:, :max_bins // 8])
+    oracle.detect_f32(one, H, ta_np, cap=cap, nthreads=1)
+    dt1 = time.perf_counter() - t1
+    return {"value": pts / dt, "unit": "points/s", "cores": threads, "kind": "oracle",
+            "sample": "first %d bins x %d templates of the same plane (%.1f M points), "
+                      "%.2f s on %d threads; 1 thread on %d bins: %.3g points/s"
+                      % (max_bins, sample.shape[0], pts / 1e6, dt, threads, max_bins // 8,
+                         one.size / dt1)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-variants", action="store_true")
+    ap.add_argument("--cpu-bins", type=int, default=1 << 21)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run one plain device copy of the FOP's size (counter scale)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: the harmonic-summing path here runs on a single "
+              "MI355X (--gpus %d is not supported)" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+
+    import paper_1805_12258_amd as hs
+    import synth
+
+    cfg = synth.SKA
+    T, N, H = cfg["n_temp"], cfg["n_chan"], cfg["n_hp"]
+    dev = torch.device("cuda:0")
+    fop = synth.make_ska(device=dev)
+    ta_np = synth.thresholds(H, T)
+    ta = torch.from_numpy(ta_np).to(dev)
+    capacity = 1 << 22
+    plan = hs.Plan(T, N, H)
+    torch.cuda.synchronize()
+
+    if args.copy_calibration:
+        dst = torch.empty_like(fop)
+        for _ in range(3):
+            dst.copy_(fop)
+        torch.cuda.synchronize()
+        del dst
+
+    r = time_detect(plan, fop, ta, capacity, args.steps, args.warmup)
+    points = T * N
+    n_cand = int(r["counts"][-1])
+    alg_bytes = points * 4 + 8 * n_cand + 8 * (H + 1)
+    achieved = alg_bytes / (r["launch_ms"] * 1e-3) / 1e9
+    tr = stored_traffic()
+    traffic = None
+    if tr is not None:
+        traffic = tr["fetch_bytes"] + tr["write_bytes"]
+
+    line = {
+        "metric": "harmonic-summed FOP points/s (85x2^21 fp32, 8 planes, full detection)",
+        "value": points / (r["ms_per_step"] * 1e-3),
+        "unit": "points/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": r["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic: Exp(1) noise + 50 injected harmonic signals, seed 2",
+        "config": {"workload": "ska-plain", "n_temp": T, "n_chan": N, "n_hp": H,
+                   "thresholds": "k+6*sqrt(k)", "candidates": n_cand},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "kernel": "k_fused<float,8,detect>", "launch_ms": r["launch_ms"],
+                     "algorithmic_bytes": alg_bytes},
+        "hbm_gbs": achieved,
+        "plane_points_per_s": H * points / (r["ms_per_step"] * 1e-3),
+    }
+
+    if not args.no_variants:
+        var = {}
+        for name, dt in (("f16", torch.float16), ("bf16", torch.bfloat16)):
+            scale = synth.PRECISION["input_scale"]
+            store = synth.quantize(fop, dt, scale)
+            p2 = hs.Plan(T, N, H, dtype=name, input_scale=scale)
+            r2 = time_detect(p2, store, ta, capacity, max(20, args.steps // 2), 5)
+            ab = points * 2 + 8 * int(r2["counts"][-1]) + 8 * (H + 1)
+            var[name] = {"value": points / (r2["ms_per_step"] * 1e-3),
+                         "ms_per_step": r2["ms_per_step"], "launch_ms": r2["launch_ms"],
+                         "hbm_gbs": ab / (r2["launch_ms"] * 1e-3) / 1e9,
+                         "vs_f32": r["ms_per_step"] / r2["ms_per_step"],
+                         "candidates": int(r2["counts"][-1])}
+            del store
+        line["variants"] = var
+
+    if not args.no_cpu:
+        fop_cpu = fop[:, :args.cpu_bins].cpu()
+        line["cpu_baseline"] = cpu_baseline(fop_cpu, H, ta_np, args.cpu_bins)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -77,7 +77,7 @@ typedef struct hs_plan_desc {
     int32_t n_hp;              /* N_hp, 1..16 (Sec. III: 8)                      */
     int32_t dtype;             /* hs_dtype of the stored FOP                     */
     float input_scale;         /* stored = power * input_scale; a power of two;  */
-                               /* 0 means 1                                      */
+                               /* 0 means 1; must be 1 for HS_DTYPE_F32          */
     int32_t n_fops;            /* 0: single FOP; >= 1: batch of n_fops FOPs      */
     const int64_t* n_chans;    /* HOST array [n_fops]: bins of each FOP          */
     int32_t tile_rows;         /* tuning: rows per tile, 0 = planner's choice    */

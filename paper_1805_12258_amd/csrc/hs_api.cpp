@@ -30,7 +30,7 @@ int ld_align(int dtype) { return dtype == HS_DTYPE_F32 ? 4 : 8; }
 
 // Largest LDS footprint the planner gives one block, so that two blocks fit
 // in the 160 KiB of a gfx950 compute unit.
-constexpr int kLdsBudget = 78 * 1024;
+constexpr int kLdsBudget = 80 * 1024;
 
 hs_status from_hip(hipError_t e) { return e == hipSuccess ? HS_OK : HS_ERR_HIP; }
 
@@ -55,10 +55,37 @@ hsk::TileArgs tile_args(const hs_plan* p, const void* fop, int64_t ld)
     a.inv_scale = 1.0f / p->scale;
     a.s_row = p->s_row;
     a.s_bin = p->s_bin;
+    a.kmask = (1u << p->s_k) - 1u;
     return a;
 }
 
 int64_t bin_tiles(int64_t n) { return (n + hsk::kTileBins - 1) / hsk::kTileBins; }
+
+// Compute units of the current device (cached per device).
+int cu_count()
+{
+    static int cache[64] = {0};
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 256;
+    if (!cache[dev]) {
+        int n = 0;
+        if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || n < 1)
+            n = 256;
+        cache[dev] = n;
+    }
+    return cache[dev];
+}
+
+// Persistent grid: blocks that fit the compute units at once.
+int persistent_grid(const hs_plan* p, int64_t tiles)
+{
+    int per_cu = (160 * 1024) / p->lds_bytes;
+    if (per_cu > 2048 / hsk::kThreads) per_cu = 2048 / hsk::kThreads;
+    if (per_cu < 1) per_cu = 1;
+    int64_t g = p->persistent_blocks > 0 ? p->persistent_blocks : (int64_t)cu_count() * per_cu;
+    if (g > tiles) g = tiles;
+    return (int)(g < 1 ? 1 : g);
+}
 
 }  // namespace
 
@@ -75,6 +102,7 @@ hs_status hs_plan_create(hs_plan** out, const hs_plan_desc* d)
             return HS_ERR_INVALID;
         const float scale = d->input_scale == 0.0f ? 1.0f : d->input_scale;
         if (!is_pow2_scale(scale)) return HS_ERR_INVALID;
+        if (d->dtype == HS_DTYPE_F32 && scale != 1.0f) return HS_ERR_INVALID;
         if (d->n_fops < 0) return HS_ERR_INVALID;
         if (d->tile_rows < 0 || d->persistent_blocks < 0) return HS_ERR_INVALID;
 
@@ -104,21 +132,24 @@ hs_status hs_plan_create(hs_plan** out, const hs_plan_desc* d)
         if (p->s_bin + p->s_k + s_r > 32) { delete p; return HS_ERR_INVALID; }
         p->s_row = p->s_bin + p->s_k;
 
-        // Rows per tile: the whole column when the staged ranges fit the LDS
-        // budget, else the largest row block that does.
-        int R = d->tile_rows > 0 ? (int)std::min<int64_t>(d->tile_rows, p->T) : (int)p->T;
-        if (d->tile_rows == 0) {
-            // the staged region is addressed by LDS-DMA through M0: keep it
-            // below 64 KiB
-            while (R > 1 && (hsk::fused_lds_bytes((int)p->T, R, p->H, hsk::kModeDetect) > kLdsBudget ||
-                             hsk::fused_stage_words((int)p->T, R, p->H) * 4 > 65536))
-                R = (R + 1) / 2;
+        // Rows per tile: at most kMaxTileRows, the row blocks as even as
+        // possible.  For an odd plane height this puts the negative template
+        // indices and the non-negative ones in different tiles, which stage
+        // disjoint source rows (floor keeps the sign).
+        int R;
+        if (d->tile_rows > 0) {
+            R = (int)std::min<int64_t>(d->tile_rows, p->T);
+        } else {
+            const int64_t blocks = (p->T + hsk::kMaxTileRows - 1) / hsk::kMaxTileRows;
+            R = (int)((p->T + blocks - 1) / blocks);
         }
+        if (R > hsk::kMaxTileRows) { delete p; return HS_ERR_UNSUPPORTED; }
         p->tile_rows = R;
         p->row_blocks = (int)((p->T + R - 1) / R);
         p->lds_bytes = hsk::fused_lds_bytes((int)p->T, R, p->H, hsk::kModeDetect);
-        if (p->lds_bytes > 160 * 1024 ||
-            hsk::fused_stage_words((int)p->T, R, p->H) * 4 > 65536) {
+        // the staged region is addressed by LDS-DMA through M0: keep it below
+        // 64 KiB; two blocks must fit one compute unit's 160 KiB
+        if (p->lds_bytes > kLdsBudget || hsk::fused_stage_words((int)p->T, R, p->H) * 4 > 65536) {
             delete p;
             return HS_ERR_UNSUPPORTED;
         }
@@ -198,7 +229,8 @@ hs_status hs_sum(const hs_plan* p, const void* fop, int64_t ld, float* hp, void*
         hsk::TileArgs a = tile_args(p, fop, ld);
         a.hp = hp;
         return from_hip(hsk::launch_fused(hsk::kModeSum, p->dtype, p->H, a, p->tiles_total,
-                                          p->lds_bytes, (hipStream_t)stream));
+                                          persistent_grid(p, p->tiles_total), p->lds_bytes,
+                                          (hipStream_t)stream));
     } catch (...) {
         return HS_ERR_HIP;
     }
@@ -220,7 +252,7 @@ hs_status hs_detect(const hs_plan* p, const void* fop, int64_t ld, const float* 
         a.cap = capacity;
         a.counts = reinterpret_cast<unsigned long long*>(counts);
         return from_hip(hsk::launch_fused(hsk::kModeDetect, p->dtype, p->H, a, p->tiles_total,
-                                          p->lds_bytes, s));
+                                          persistent_grid(p, p->tiles_total), p->lds_bytes, s));
     } catch (...) {
         return HS_ERR_HIP;
     }
@@ -276,16 +308,8 @@ hs_status hs_detect_batched(const hs_plan* p, const void* const* fops, const int
         b.counts = reinterpret_cast<unsigned long long*>(counts);
         b.s_row = p->s_row;
         b.s_bin = p->s_bin;
-        int grid = p->persistent_blocks;
-        if (grid == 0) {
-            hipDeviceProp_t prop;
-            if (hipGetDeviceProperties(&prop, dev) != hipSuccess) return HS_ERR_HIP;
-            int per_cu = (160 * 1024) / p->lds_bytes;
-            if (per_cu > 4) per_cu = 4;
-            if (per_cu < 1) per_cu = 1;
-            grid = prop.multiProcessorCount * per_cu;
-        }
-        if ((int64_t)grid > p->tiles_total) grid = (int)p->tiles_total;
+        b.kmask = (1u << p->s_k) - 1u;
+        const int grid = persistent_grid(p, p->tiles_total);
         return from_hip(hsk::launch_batched(p->dtype, p->H, b, grid, p->lds_bytes, s));
     } catch (...) {
         return HS_ERR_HIP;

@@ -6,9 +6,9 @@
 
 namespace hsk {
 
-hipError_t launch_fused_f32(int mode, int H, const TileArgs& a, int64_t n, int lds, hipStream_t s);
-hipError_t launch_fused_f16(int mode, int H, const TileArgs& a, int64_t n, int lds, hipStream_t s);
-hipError_t launch_fused_bf16(int mode, int H, const TileArgs& a, int64_t n, int lds, hipStream_t s);
+hipError_t launch_fused_f32(int mode, int H, const TileArgs& a, int64_t n, int g, int lds, hipStream_t s);
+hipError_t launch_fused_f16(int mode, int H, const TileArgs& a, int64_t n, int g, int lds, hipStream_t s);
+hipError_t launch_fused_bf16(int mode, int H, const TileArgs& a, int64_t n, int g, int lds, hipStream_t s);
 hipError_t launch_batched_f32(int H, const BatchArgs& b, int grid, int lds, hipStream_t s);
 hipError_t launch_batched_f16(int H, const BatchArgs& b, int grid, int lds, hipStream_t s);
 hipError_t launch_batched_bf16(int H, const BatchArgs& b, int grid, int lds, hipStream_t s);
@@ -42,13 +42,13 @@ int fused_lds_bytes(int T, int R, int H, int mode)
     return fused_stage_words(T, R, H) * 4 + smem_tail_bytes(R, H);
 }
 
-hipError_t launch_fused(int mode, int dtype, int H, const TileArgs& a, int64_t n_tiles, int lds_bytes,
-                        hipStream_t s)
+hipError_t launch_fused(int mode, int dtype, int H, const TileArgs& a, int64_t n_tiles, int grid,
+                        int lds_bytes, hipStream_t s)
 {
     switch (dtype) {
-    case HS_DTYPE_F32: return launch_fused_f32(mode, H, a, n_tiles, lds_bytes, s);
-    case HS_DTYPE_F16: return launch_fused_f16(mode, H, a, n_tiles, lds_bytes, s);
-    case HS_DTYPE_BF16: return launch_fused_bf16(mode, H, a, n_tiles, lds_bytes, s);
+    case HS_DTYPE_F32: return launch_fused_f32(mode, H, a, n_tiles, grid, lds_bytes, s);
+    case HS_DTYPE_F16: return launch_fused_f16(mode, H, a, n_tiles, grid, lds_bytes, s);
+    case HS_DTYPE_BF16: return launch_fused_bf16(mode, H, a, n_tiles, grid, lds_bytes, s);
     }
     return hipErrorInvalidValue;
 }

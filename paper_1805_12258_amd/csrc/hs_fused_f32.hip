@@ -4,9 +4,9 @@
 namespace hsk {
 
 template <int H>
-static hipError_t fused_one(int mode, const TileArgs& a, int64_t n, int lds, hipStream_t s)
+static hipError_t fused_one(int mode, const TileArgs& a, int64_t n, int g, int lds, hipStream_t s)
 {
-    return launch_fused_t<float, H>(mode, a, n, lds, s);
+    return launch_fused_t<float, H>(mode, a, n, g, lds, s);
 }
 
 template <int H>
@@ -15,9 +15,9 @@ static hipError_t batched_one(const BatchArgs& b, int grid, int lds, hipStream_t
     return launch_batched_t<float, H>(b, grid, lds, s);
 }
 
-hipError_t launch_fused_f32(int mode, int H, const TileArgs& a, int64_t n, int lds, hipStream_t s)
+hipError_t launch_fused_f32(int mode, int H, const TileArgs& a, int64_t n, int g, int lds, hipStream_t s)
 {
-    HS_H_CASES(fused_one, mode, a, n, lds, s)
+    HS_H_CASES(fused_one, mode, a, n, g, lds, s)
 }
 
 hipError_t launch_batched_f32(int H, const BatchArgs& b, int grid, int lds, hipStream_t s)

@@ -2,19 +2,26 @@
 // arXiv:1805.12258, Sec. III) with threshold detection, or materialised.
 //
 // Work decomposition (the paper's MultipleHP idea, Sec. IV-C, rebuilt for a
-// GPU): a tile is a block of template rows x kTileBins consecutive bins.  For
-// each stretch factor m >= 2 the tile reads only the shrunken source range
-// rows floor(i/m), bins [floor(j0/m), floor((j0+B-1)/m)] of the FOP; these
-// ranges are staged in LDS once per tile (for fp32 straight from global
-// memory with LDS-DMA loads).  Each lane owns kV consecutive bins of one row
-// at a time and keeps the kV partial sums in registers; HP_k is formed for
-// k = 1..H in order (Eq. 2), compared with its row threshold and, in the
-// materialising mode, stored.  No intermediate plane goes to memory in the
-// detection mode.
+// GPU): a tile is a block of at most kMaxTileRows template rows x kTileBins
+// consecutive bins.  For each stretch factor m >= 2 the tile reads only the
+// shrunken source range (rows floor(i/m), bins [floor(j0/m),
+// floor((j0+B-1)/m)]); these ranges are staged in LDS once per tile, for fp32
+// straight from global memory with LDS-DMA loads.  Each lane owns kV
+// consecutive bins of one row at a time and keeps the kV partial sums in
+// registers; HP_k is formed for k = 1..H in order (Eq. 2), compared with its
+// row threshold and, in the materialising mode, stored.  No intermediate
+// plane goes to memory in the detection mode.
 //
-// Candidates are compacted through a per-block LDS buffer (wave-aggregated
-// LDS atomics) and written out with one global atomic per block; a buffer
-// overflow spills straight to global memory with per-wave atomics.
+// Latency: all loads a wave needs for a tile (its share of the staging and
+// the m = 1 values of all its rows) are issued together at the start of the
+// tile, so a tile costs one memory round trip; several blocks per compute
+// unit overlap one another's round trips.  The grid is persistent: block b
+// walks a contiguous chunk of tiles.
+//
+// Candidates: each wave appends its hits to a private LDS buffer (ballot +
+// mbcnt, no atomics) and keeps per-plane counts in scalar registers.  A full
+// buffer is written out with one global atomic per wave; per-plane counts
+// are reduced through LDS and added to global memory once per block and FOP.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -52,6 +59,13 @@ template <> struct Io<_Float16> {
     }
 };
 
+// Reduced-precision storage holds power * scale with scale a power of two;
+// converting each stored value to fp32 and multiplying by 1/scale is exact,
+// and power-of-two scaling commutes with every fp32 rounding of the sums, so
+// the planes come out in power units, bitwise equal to the scaled-storage
+// sums divided by scale.
+template <typename TIn> struct Scaled { static constexpr bool value = !std::is_same<TIn, float>::value; };
+
 template <> struct Io<bf16_t> {
     using T = bf16_t;
     static __device__ __forceinline__ float one(const T* p)
@@ -83,75 +97,79 @@ __device__ __forceinline__ void static_for(F&& f)
 // Shared-memory carve-up of one block.
 struct Smem {
     float* stage;                 // staged source rows, all m >= 2
-    float* thr;                   // [R][H] thresholds * scale
-    uint2* cand;                  // [kCandCap]
-    int* cnt;                     // [0]: buffered candidates, [k]: plane k
-    unsigned long long* base;     // global slot of the buffer
+    uint2* cand;                  // [kWaves][kWaveCandCap] per-wave candidate buffers
+    int* cnt;                     // [kMaxH] per-plane counts of the block
 };
 
-template <int H>
-__device__ __forceinline__ Smem carve(float* lds, int stage_words, int R)
+__device__ __forceinline__ Smem carve(float* lds, int stage_words, int R, int H)
 {
     Smem s;
+    (void)R;
+    (void)H;
     s.stage = lds;
-    s.thr = lds + stage_words;
-    const int thr_words = (R * H + 3) & ~3;
-    s.cand = reinterpret_cast<uint2*>(s.thr + thr_words);
-    s.base = reinterpret_cast<unsigned long long*>(s.cand + kCandCap);
-    s.cnt = reinterpret_cast<int*>(s.base + 1);
+    s.cand = reinterpret_cast<uint2*>(lds + stage_words);
+    s.cnt = reinterpret_cast<int*>(s.cand + kWaves * kWaveCandCap);
     return s;
 }
 
-
+// Per-wave detection state (a wave-uniform value).
 template <int H>
-__device__ __forceinline__ void push_cand(const Smem& sh, hs_cand* out, int64_t cap,
-                                          unsigned long long* counts, uint32_t key, float pw, int k)
+struct WaveState {
+    int n;          // entries in the wave's LDS buffer
+};
+
+__device__ __forceinline__ uint64_t read_first_u64(uint64_t x)
 {
-    const int pos = atomicAdd(&sh.cnt[0], 1);
-    if (pos < kCandCap) {
-        sh.cand[pos] = make_uint2(key, __float_as_uint(pw));
-    } else {
-        const unsigned long long g = atomicAdd(&counts[H], 1ull);
-        if ((int64_t)g < cap) {
-            reinterpret_cast<uint2*>(out)[g] = make_uint2(key, __float_as_uint(pw));
-        }
-    }
-    atomicAdd(&sh.cnt[k], 1);
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)x);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(x >> 32));
+    return ((uint64_t)hi << 32) | lo;
 }
 
-// Write the block's buffered candidates and per-plane counts to global memory
-// and reset the buffer.  Called by the whole block, after a barrier.
-template <int H>
-__device__ __forceinline__ void flush_cands(const Smem& sh, hs_cand* out, int64_t cap,
-                                            unsigned long long* counts)
+// Write a wave's buffered candidates to global memory (one atomic per wave)
+// and count them per plane in the block's LDS counters (the plane is read
+// back from each candidate word).
+__device__ __forceinline__ void flush_wave(const uint2* wbuf, int n, hs_cand* out, int64_t cap,
+                                           unsigned long long* total, int* block_cnt, int s_bin,
+                                           uint32_t kmask)
 {
-    const int tid = threadIdx.x;
-    if (tid == 0) {
-        const int n = min(sh.cnt[0], kCandCap);
-        *sh.base = n ? atomicAdd(&counts[H], (unsigned long long)n) : 0ull;
-        sh.cnt[0] = n;
+    const int lane = threadIdx.x & 63;
+    unsigned long long base = 0;
+    if (lane == 0) base = atomicAdd(total, (unsigned long long)n);
+    base = read_first_u64(base);
+    for (int e = lane; e < n; e += 64) {
+        const uint2 c = wbuf[e];
+        atomicAdd(&block_cnt[(c.x >> s_bin) & kmask], 1);
+        if ((int64_t)(base + e) < cap) reinterpret_cast<uint2*>(out)[base + e] = c;
     }
-    if (tid >= 1 && tid <= H) {
-        const int n = sh.cnt[tid];
-        if (n) atomicAdd(&counts[tid - 1], (unsigned long long)n);
-    }
-    __syncthreads();
-    const int n = sh.cnt[0];
-    const unsigned long long base = *sh.base;
-    for (int e = tid; e < n; e += kThreads) {
-        if ((int64_t)(base + e) < cap) reinterpret_cast<uint2*>(out)[base + e] = sh.cand[e];
-    }
-    __syncthreads();
-    if (tid <= H) sh.cnt[tid] = 0;
 }
 
-// One tile: stage, form the planes, detect or store.
+// Add the block's per-plane counts to global memory and clear them.  Called
+// by the whole block; contains barriers.
+template <int H>
+__device__ __forceinline__ void flush_counts(const Smem& sh, unsigned long long* counts)
+{
+    __syncthreads();
+    if (threadIdx.x < H) {
+        const int v = sh.cnt[threadIdx.x];
+        if (v) atomicAdd(&counts[threadIdx.x], (unsigned long long)v);
+        sh.cnt[threadIdx.x] = 0;
+    }
+    __syncthreads();
+}
+
+// One tile: stage, form the planes, detect or store.  Starts and ends with a
+// barrier so the staging buffer is free when it is refilled.
 template <typename TIn, int H, int MODE>
-__device__ __forceinline__ void run_tile(const TileArgs& a, int64_t tile, const Smem& sh)
+__device__ __forceinline__ void run_tile(const TileArgs& a, int64_t tile, const Smem& sh,
+                                         WaveState<H>& ws)
 {
     using Ld = Io<TIn>;
     using T = typename Ld::T;
     const T* __restrict__ fop = reinterpret_cast<const T*>(a.fop);
+    // thresholds are read-only for the whole launch: read them through the
+    // constant address space so uniform reads become scalar loads
+    const __attribute__((address_space(4))) float* ta =
+        (const __attribute__((address_space(4))) float*)a.ta;
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
 
@@ -172,15 +190,17 @@ __device__ __forceinline__ void run_tile(const TileArgs& a, int64_t tile, const 
     int tot = 0;
 #pragma unroll
     for (int m = 2; m <= H; ++m) {
-        a_lo[m] = (int)floordiv(i_lo, m);
-        nrow[m] = (int)floordiv(i_hi, m) - a_lo[m] + 1;
+        a_lo[m] = floordiv32(i_lo, m);
+        nrow[m] = floordiv32(i_hi, m) - a_lo[m] + 1;
         blo[m] = j0 / m;
         span[m] = (int)((jend - 1) / m - blo[m] + 1);
         offm[m] = tot;
         tot += nrow[m] * stage_pitch(m);
     }
 
-    // Stage the shrunken source ranges.
+    __syncthreads();   // the previous tile is done with the staging buffer
+
+    // 1. Stage the shrunken source ranges (this wave's rows of each region).
 #pragma unroll
     for (int m = 2; m <= H; ++m) {
         for (int row = wave; row < nrow[m]; row += kWaves) {
@@ -193,23 +213,39 @@ __device__ __forceinline__ void run_tile(const TileArgs& a, int64_t tile, const 
                         __builtin_amdgcn_global_load_lds(src + col, (lds_ptr_t)(dst + ch * 64), 4, 0, 0);
                     }
                 } else {
-                    if (col < span[m]) dst[col] = Ld::one(src + col);
+                    if (col < span[m]) dst[col] = Ld::one(src + col) * a.inv_scale;
                 }
             }
         }
     }
-    if constexpr (MODE == kModeDetect) {
-        for (int e = threadIdx.x; e < nr * H; e += kThreads) {
-            const int rr = e / H, k = e - rr * H;
-            sh.thr[e] = a.ta[(int64_t)k * a.T + r0 + rr] * a.scale;
-        }
-    }
 
-    // Per-lane view of the staged rows.
+    // 2. The m = 1 values of every row this wave owns.
     const int64_t jb = j0 + kV * lane;
     bool valid[kV];
 #pragma unroll
     for (int v = 0; v < kV; ++v) valid[v] = jb + v < N;
+    const bool tile_full = j0 + kTileBins <= N;        // wave-uniform
+    float x[kRowsPerWave][kV];
+    if (tile_full) {
+#pragma unroll
+        for (int q = 0; q < kRowsPerWave; ++q) {
+            const int rr = wave + kWaves * q;
+            if (rr < nr) Ld::four(fop + (int64_t)(r0 + rr) * ld + jb, x[q]);
+        }
+    } else {
+#pragma unroll
+        for (int q = 0; q < kRowsPerWave; ++q) {
+            const int rr = wave + kWaves * q;
+            const T* p = fop + (int64_t)(r0 + rr) * ld + jb;
+#pragma unroll
+            // bins past the end start at -inf: no sum of them can pass a
+            // threshold (-inf + x is -inf or NaN)
+            for (int v = 0; v < kV; ++v)
+                x[q][v] = (rr < nr && valid[v]) ? Ld::one(p + v) : -__builtin_inff();
+        }
+    }
+
+    // Per-lane view of the staged rows.
     int loff[H + 1], sig[H + 1];
 #pragma unroll
     for (int m = 2; m <= H; ++m) {
@@ -219,62 +255,80 @@ __device__ __forceinline__ void run_tile(const TileArgs& a, int64_t tile, const 
         sig[m] = t % m;
     }
 
-    // First row's m = 1 values (overlaps the staging loads).
-    auto load_row = [&](int r, float* x) {
-        const T* p = fop + (int64_t)r * ld + jb;
-        if (jb + kV <= N) {
-            Ld::four(p, x);
-        } else {
-#pragma unroll
-            for (int v = 0; v < kV; ++v) x[v] = valid[v] ? Ld::one(p + v) : 0.0f;
-        }
-    };
-    float xn[kV];
-    if (wave < nr) load_row(r0 + wave, xn);
-
     __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
 
-    for (int rr = wave; rr < nr; rr += kWaves) {
+    uint2* wbuf = sh.cand + wave * kWaveCandCap;
+#pragma unroll
+    for (int q = 0; q < kRowsPerWave; ++q) {
+        const int rr = wave + kWaves * q;
+        if (rr >= nr) break;
         const int r = r0 + rr;
         const int i = r - c;
-        float acc[kV];
-#pragma unroll
-        for (int v = 0; v < kV; ++v) acc[v] = xn[v];
-        if (rr + kWaves < nr) load_row(r + kWaves, xn);
-
+        // All LDS reads of the row first (thresholds and staged source
+        // words), so their latencies overlap; the candidate writes below
+        // could otherwise alias them and serialise every read.
         float thr[H];
         if constexpr (MODE == kModeDetect) {
 #pragma unroll
-            for (int k = 0; k < H; ++k) thr[k] = sh.thr[rr * H + k];
+            for (int k = 0; k < H; ++k) thr[k] = ta[k * a.T + r];
         }
+        float w[H + 1][2];
+        static_for<2, H>([&](auto mc) {
+            constexpr int m = decltype(mc)::value;
+            const int srow = floordiv32(i, m) - a_lo[m];
+            const float* p = sh.stage + loff[m] + srow * stage_pitch(m);
+            if constexpr (kV % m == 0) {
+#pragma unroll
+                for (int u = 0; u < kV / m; ++u) w[m][u] = p[u];
+            } else if constexpr (m % kV == 0) {
+                w[m][0] = p[0];
+            } else {
+                w[m][0] = p[0];
+                w[m][1] = p[1];
+            }
+        });
+
+        float acc[kV];
+#pragma unroll
+        for (int v = 0; v < kV; ++v) acc[v] = Scaled<TIn>::value ? x[q][v] * a.inv_scale : x[q][v];
 
         auto emit = [&](int k) {
             if constexpr (MODE == kModeDetect) {
                 const float t = thr[k - 1];
                 bool hit[kV];
-                bool any = false;
+                uint64_t mk[kV];
+                uint64_t mall = 0;
 #pragma unroll
                 for (int v = 0; v < kV; ++v) {
-                    hit[v] = valid[v] && (acc[v] > t);
-                    any |= hit[v];
+                    hit[v] = acc[v] > t;
+                    mk[v] = __builtin_amdgcn_ballot_w64(hit[v]);
+                    mall |= mk[v];
                 }
-                if (any) {
-                    const uint32_t hi = (uint32_t)(((uint64_t)r << a.s_row) | ((uint64_t)(k - 1) << a.s_bin));
+                if (mall) {
+                    // room for every hit of this (row, plane): at most kV per lane
+                    if (ws.n > kWaveCandCap - kV * 64) {
+                        flush_wave(wbuf, ws.n, a.out, a.cap, &a.counts[H], sh.cnt, a.s_bin, a.kmask);
+                        ws.n = 0;
+                    }
+                    const uint32_t hi =
+                        (uint32_t)(((uint64_t)r << a.s_row) | ((uint64_t)(k - 1) << a.s_bin));
 #pragma unroll
                     for (int v = 0; v < kV; ++v) {
-                        if (hit[v]) {
-                            push_cand<H>(sh, a.out, a.cap, a.counts, hi | (uint32_t)(jb + v),
-                                         acc[v] * a.inv_scale, k);
+                        if (mk[v]) {
+                            if (hit[v]) {
+                                const int pos = ws.n + (int)__builtin_amdgcn_mbcnt_hi(
+                                    (uint32_t)(mk[v] >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mk[v], 0));
+                                wbuf[pos] = make_uint2(hi | (uint32_t)(jb + v), __float_as_uint(acc[v]));
+                            }
+                            ws.n += __builtin_popcountll(mk[v]);
                         }
                     }
                 }
             } else {
                 float* dst = a.hp + ((int64_t)(k - 1) * a.T + r) * N + jb;
-                float y[kV];
-#pragma unroll
-                for (int v = 0; v < kV; ++v) y[v] = acc[v] * a.inv_scale;
-                if (jb + kV <= N && (N & 3) == 0) {
+                const float* y = acc;
+                if (tile_full && (N & 3) == 0) {
                     *reinterpret_cast<float4*>(dst) = make_float4(y[0], y[1], y[2], y[3]);
                 } else {
 #pragma unroll
@@ -287,28 +341,21 @@ __device__ __forceinline__ void run_tile(const TileArgs& a, int64_t tile, const 
         emit(1);
         static_for<2, H>([&](auto mc) {
             constexpr int m = decltype(mc)::value;
-            const int srow = (int)floordiv(i, m) - a_lo[m];
-            const float* p = sh.stage + loff[m] + srow * stage_pitch(m);
             if constexpr (kV % m == 0) {
-                float w[kV / m];
 #pragma unroll
-                for (int q = 0; q < kV / m; ++q) w[q] = p[q];
-#pragma unroll
-                for (int v = 0; v < kV; ++v) acc[v] = acc[v] + w[v / m];
+                for (int v = 0; v < kV; ++v) acc[v] = acc[v] + w[m][v / m];
             } else if constexpr (m % kV == 0) {
-                const float w0 = p[0];
 #pragma unroll
-                for (int v = 0; v < kV; ++v) acc[v] = acc[v] + w0;
+                for (int v = 0; v < kV; ++v) acc[v] = acc[v] + w[m][0];
             } else {
-                // lane's kV bins span two source words: bin jb+v reads word
-                // floor((sig + v)/m) of the lane's window
-                const float w0 = p[0], w1 = p[1];
+                // the lane's kV bins span two source words: bin jb+v reads
+                // word floor((sig + v)/m) of the lane's window
 #pragma unroll
                 for (int v = 0; v < kV; ++v) {
-                    const int q = v / m, s = v % m;
+                    const int qv = v / m, s = v % m;
                     float val;
-                    if (s == 0) val = q ? w1 : w0;
-                    else val = (sig[m] >= m - s) ? w1 : w0;
+                    if (s == 0) val = qv ? w[m][1] : w[m][0];
+                    else val = (sig[m] >= m - s) ? w[m][1] : w[m][0];
                     acc[v] = acc[v] + val;
                 }
             }
@@ -317,44 +364,61 @@ __device__ __forceinline__ void run_tile(const TileArgs& a, int64_t tile, const 
     }
 }
 
+// Tiles [t_begin, t_end) of block b for a grid of g blocks over n tiles.
+__device__ __forceinline__ void block_chunk(int64_t n, int64_t& t_begin, int64_t& t_end)
+{
+    const int64_t g = gridDim.x, b = blockIdx.x;
+    const int64_t q = n / g, r = n % g;
+    t_begin = b * q + (b < r ? b : r);
+    t_end = t_begin + q + (b < r ? 1 : 0);
+}
+
 template <typename TIn, int H, int MODE>
-__global__ __launch_bounds__(kThreads) void k_fused(TileArgs a, int stage_words)
+__global__ __launch_bounds__(kThreads) void k_fused(TileArgs a, int stage_words, int64_t n_tiles)
 {
     extern __shared__ __align__(16) float lds[];
-    const Smem sh = carve<H>(lds, stage_words, a.R);
+    const Smem sh = carve(lds, stage_words, a.R, H);
+    WaveState<H> ws;
+    ws.n = 0;
+    if (threadIdx.x < kMaxH) sh.cnt[threadIdx.x] = 0;
+
+    int64_t t0, t1;
+    block_chunk(n_tiles, t0, t1);
+    for (int64_t t = t0; t < t1; ++t) run_tile<TIn, H, MODE>(a, t, sh, ws);
+
     if constexpr (MODE == kModeDetect) {
-        if (threadIdx.x <= H) sh.cnt[threadIdx.x] = 0;
-    }
-    run_tile<TIn, H, MODE>(a, blockIdx.x, sh);
-    if constexpr (MODE == kModeDetect) {
-        __syncthreads();
-        flush_cands<H>(sh, a.out, a.cap, a.counts);
+        if (ws.n) flush_wave(sh.cand + (threadIdx.x >> 6) * kWaveCandCap, ws.n, a.out, a.cap,
+                             &a.counts[H], sh.cnt, a.s_bin, a.kmask);
+        flush_counts<H>(sh, a.counts);
     }
 }
 
-// Batched persistent kernel: a fixed grid walks the tiles of every FOP.
+// Batched persistent kernel: the grid walks the tiles of every FOP.
 template <typename TIn, int H>
 __global__ __launch_bounds__(kThreads) void k_batched(BatchArgs b, int stage_words)
 {
     extern __shared__ __align__(16) float lds[];
-    const Smem sh = carve<H>(lds, stage_words, b.R);
-    if (threadIdx.x <= H) sh.cnt[threadIdx.x] = 0;
+    const Smem sh = carve(lds, stage_words, b.R, H);
+    WaveState<H> ws;
+    ws.n = 0;
+    if (threadIdx.x < kMaxH) sh.cnt[threadIdx.x] = 0;
     constexpr int align_elems = sizeof(typename Io<TIn>::T) == 4 ? 4 : 8;
 
-    int f = 0;
-    int64_t t = blockIdx.x;
-    // first FOP holding tile t (binary search over the prefix of tile counts)
+    int64_t t0, t1;
+    block_chunk(b.tiles_total, t0, t1);
+    if (t0 >= t1) return;
+    // FOP holding tile t0 (binary search over the prefix of tile counts)
+    int f;
     {
         int lo = 0, hi = b.n_fops - 1;
         while (lo < hi) {
             const int mid = (lo + hi + 1) >> 1;
-            if (b.tile_prefix[mid] <= t) lo = mid; else hi = mid - 1;
+            if (b.tile_prefix[mid] <= t0) lo = mid; else hi = mid - 1;
         }
-        f = lo;
+        f = __builtin_amdgcn_readfirstlane(lo);
     }
-    for (; t < b.tiles_total; t += gridDim.x) {
-        while (t >= b.tile_prefix[f + 1]) ++f;
-        f = __builtin_amdgcn_readfirstlane(f);
+    for (int64_t tf = t0; tf < t1; ++f) {
+        const int64_t fb = b.tile_prefix[f], fe = min(b.tile_prefix[f + 1], t1);
         TileArgs a;
         a.fop = b.fops[f];
         a.ld = b.lds[f];
@@ -371,32 +435,38 @@ __global__ __launch_bounds__(kThreads) void k_batched(BatchArgs b, int stage_wor
         a.counts = b.counts + (int64_t)f * (H + 1);
         a.s_row = b.s_row;
         a.s_bin = b.s_bin;
+        a.kmask = b.kmask;
         a.hp = nullptr;
         const bool ok = ((reinterpret_cast<uintptr_t>(a.fop) & 15) == 0) &&
                         (a.ld % align_elems == 0) && a.ld >= a.N;
         if (!ok) {
-            if (threadIdx.x == 0 && t == b.tile_prefix[f]) a.counts[H] = ~0ull;
-            continue;
+            if (threadIdx.x == 0 && tf == fb) a.counts[H] = ~0ull;
+        } else {
+            for (int64_t t = tf; t < fe; ++t) run_tile<TIn, H, kModeDetect>(a, t - fb, sh, ws);
+            if (ws.n) {
+                flush_wave(sh.cand + (threadIdx.x >> 6) * kWaveCandCap, ws.n, a.out, a.cap,
+                           &a.counts[H], sh.cnt, a.s_bin, a.kmask);
+                ws.n = 0;
+            }
+            flush_counts<H>(sh, a.counts);
         }
-        run_tile<TIn, H, kModeDetect>(a, t - b.tile_prefix[f], sh);
-        __syncthreads();
-        flush_cands<H>(sh, a.out, a.cap, a.counts);
+        tf = fe;
     }
 }
 
 template <typename TIn, int H>
-static hipError_t launch_fused_t(int mode, const TileArgs& a, int64_t n_tiles, int lds_bytes,
-                                 hipStream_t s)
+static hipError_t launch_fused_t(int mode, const TileArgs& a, int64_t n_tiles, int grid,
+                                 int lds_bytes, hipStream_t s)
 {
     const int stage_words = (lds_bytes - smem_tail_bytes(a.R, H)) / 4;
     if (mode == kModeDetect) {
         auto k = k_fused<TIn, H, kModeDetect>;
         (void)hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, lds_bytes);
-        hipLaunchKernelGGL(k, dim3((unsigned)n_tiles), dim3(kThreads), lds_bytes, s, a, stage_words);
+        hipLaunchKernelGGL(k, dim3(grid), dim3(kThreads), lds_bytes, s, a, stage_words, n_tiles);
     } else {
         auto k = k_fused<TIn, H, kModeSum>;
         (void)hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, lds_bytes);
-        hipLaunchKernelGGL(k, dim3((unsigned)n_tiles), dim3(kThreads), lds_bytes, s, a, stage_words);
+        hipLaunchKernelGGL(k, dim3(grid), dim3(kThreads), lds_bytes, s, a, stage_words, n_tiles);
     }
     return hipGetLastError();
 }

@@ -11,15 +11,18 @@
 
 namespace hsk {
 
-// Tile geometry of the fused kernels.  A tile is a block of template rows
-// times kTileBins consecutive bins; each lane owns kV consecutive bins of one
-// row at a time, a wave sweeps one row of the tile per step.
+// Tile geometry of the fused kernels.  A tile is a block of at most
+// kMaxTileRows template rows times kTileBins consecutive bins; each lane owns
+// kV consecutive bins of one row at a time, and wave w of a block handles the
+// tile rows w, w + kWaves, w + 2 kWaves.
 constexpr int kLanes = 64;
 constexpr int kV = 4;
 constexpr int kTileBins = kV * kLanes;   // 256
 constexpr int kWaves = 8;
 constexpr int kThreads = kWaves * kLanes;
-constexpr int kCandCap = 512;            // LDS candidate buffer entries per block
+constexpr int kRowsPerWave = 6;
+constexpr int kMaxTileRows = kWaves * kRowsPerWave;   // 48
+constexpr int kWaveCandCap = 320;        // per-wave LDS candidate buffer (>= kV*64 + 64)
 constexpr int kMaxH = 16;
 
 // Words reserved per staged source row of stretch factor m: the largest
@@ -30,16 +33,22 @@ __host__ __device__ constexpr int stage_pitch(int m)
     return (((kTileBins + m - 2) / m + 1) + 3) & ~3;
 }
 
-// LDS bytes after the staged region: thresholds [R][H], the candidate buffer,
-// its global base slot and the per-plane counters.
+// LDS bytes after the staged region: the per-wave candidate buffers and the
+// per-plane counters of the block.
 __host__ __device__ constexpr int smem_tail_bytes(int R, int H)
 {
-    return ((R * H + 3) & ~3) * 4 + kCandCap * 8 + 8 + (kMaxH + 1) * 4;
+    return (void)R, (void)H, kWaves * kWaveCandCap * 8 + kMaxH * 4;
 }
 
 __host__ __device__ inline int64_t floordiv(int64_t a, int64_t b)
 {
     int64_t q = a / b;
+    return (q * b > a) ? q - 1 : q;
+}
+
+__host__ __device__ inline int floordiv32(int a, int b)
+{
+    int q = a / b;
     return (q * b > a) ? q - 1 : q;
 }
 
@@ -53,13 +62,14 @@ struct TileArgs {
     int32_t R;              // rows per tile
     int32_t row_blocks;     // tiles across the rows
     float scale;            // stored = power * scale
-    float inv_scale;
-    const float* ta;        // [H][T]
+    float inv_scale;        // applied when a stored value is converted to fp32
+    const float* ta;        // [H][T], unscaled
     // detect
     hs_cand* out;
     int64_t cap;
     unsigned long long* counts;   // [H+1]
     int32_t s_row, s_bin;
+    uint32_t kmask;               // (1 << s_k) - 1
     // materialised planes
     float* hp;              // [H][T][N]
 };
@@ -80,6 +90,7 @@ struct BatchArgs {
     const int64_t* caps;
     unsigned long long* counts;   // [n_fops][H+1]
     int32_t s_row, s_bin;
+    uint32_t kmask;
 };
 
 enum Mode { kModeDetect = 0, kModeSum = 1 };
@@ -91,7 +102,7 @@ int fused_lds_bytes(int T, int R, int H, int mode);
 int fused_stage_words(int T, int R, int H);
 
 hipError_t launch_fused(int mode, int dtype, int H, const TileArgs& a, int64_t n_tiles,
-                        int lds_bytes, hipStream_t s);
+                        int grid, int lds_bytes, hipStream_t s);
 hipError_t launch_batched(int dtype, int H, const BatchArgs& a, int grid, int lds_bytes,
                           hipStream_t s);
 hipError_t launch_zero_i64(int64_t* p, int64_t n, hipStream_t s);

@@ -3,6 +3,7 @@ import numpy as np
 import torch
 
 import oracle
+import synth
 
 
 def padded_device(fop_cpu, dtype=torch.float32, scale=1.0, pad=None, fill=float("nan")):
@@ -65,3 +66,45 @@ def random_thresholds(H, T, seed, base=None):
         t[rng.integers(0, H), rng.integers(0, T)] = -np.inf
         t[rng.integers(0, H), rng.integers(0, T)] = np.inf
     return t
+
+
+def make_batch(lens, T, H, seed0, dtype=torch.float32, scale=1.0):
+    """Seeded FOPs of the given lengths on cuda:0 (ld > N, NaN padding) and
+    their CPU storage copies."""
+    devs, stores = [], []
+    for f, n in enumerate(lens):
+        x = synth.noise(T, n, seed0 + f)
+        if n > 4 * H:
+            synth.inject(x, synth.draw_signals(T, n, H, 2, seed0 + f))
+        d, s = padded_device(x, dtype=dtype, scale=scale, pad=8 * (f % 3))
+        devs.append(d)
+        stores.append(s)
+    return devs, stores
+
+
+def batched_call(plan, devs, ta_np, caps):
+    """Run hs_detect_batched; returns per-FOP (idx, pw, counts)."""
+    import paper_1805_12258_amd as hs
+    dev = devs[0].device
+    fops = torch.tensor([d.data_ptr() for d in devs], dtype=torch.int64, device=dev)
+    lds = torch.tensor([d.stride(0) for d in devs], dtype=torch.int64, device=dev)
+    offs = np.concatenate([[0], np.cumsum(caps)[:-1]]).astype(np.int64)
+    out = torch.empty((int(np.sum(caps)), 2), dtype=torch.int32, device=dev)
+    counts = torch.empty((len(devs), plan.n_hp + 1), dtype=torch.int64, device=dev)
+    ta = torch.from_numpy(np.ascontiguousarray(ta_np, dtype=np.float32)).to(dev)
+    args = (fops, lds, ta, out, torch.from_numpy(offs).to(dev),
+            torch.tensor(caps, dtype=torch.int64, device=dev), counts)
+    hs.hs_detect_batched(plan.handle, *args)
+    torch.cuda.synchronize()
+    return args, offs
+
+
+def unpack_batched(out, counts, offs, caps):
+    res = []
+    c = counts.cpu().numpy()
+    o = out.cpu().numpy()
+    for f in range(len(offs)):
+        n = min(int(c[f, -1]), int(caps[f]))
+        a = o[offs[f]:offs[f] + n]
+        res.append((a[:, 0].view(np.uint32).copy(), a[:, 1].view(np.float32).copy(), c[f].copy()))
+    return res

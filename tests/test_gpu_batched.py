@@ -1,0 +1,124 @@
+"""Batched persistent launch: equal to per-FOP launches and to the oracle,
+also when replayed from a captured HIP graph."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_1805_12258_amd as hs
+import synth
+from tests.helpers import (batched_call, gpu_detect, make_batch, oracle_detect_sorted,
+                           unpack_batched)
+
+pytestmark = pytest.mark.gpu
+
+
+def triples(idx, pw, s_row, s_bin):
+    """(row, plane, bin, power bits) rows of a candidate list, sorted."""
+    idx = idx.astype(np.uint64)
+    kmask = (1 << (s_row - s_bin)) - 1
+    r = (idx >> np.uint64(s_row)).astype(np.int64)
+    k = ((idx >> np.uint64(s_bin)) & np.uint64(kmask)).astype(np.int64) + 1
+    j = (idx & np.uint64((1 << s_bin) - 1)).astype(np.int64)
+    t = np.stack([r, k, j, pw.view(np.uint32).astype(np.int64)], axis=1)
+    return t[np.lexsort(t.T[::-1])]
+
+
+def oracle_triples(store, H, ta, scale=1.0):
+    i, p, c = oracle_detect_sorted(store, H, ta, scale=scale)
+    sr, sk, sb = oracle.field_bits(store.shape[0], store.shape[1], H)
+    return triples(i, p, sb + sk, sb), c
+
+
+LENS = [1000, 4096, 300, 65536, 1, 257, 20000, 256, 3 * 256 + 5]
+
+
+@pytest.mark.parametrize("H,T", [(16, 85), (8, 21), (3, 9)])
+def test_batched_matches_oracle_and_single(H, T):
+    print("case", H, T, flush=True)
+    devs, stores = make_batch(LENS, T, H, 7000 + H)
+    ta = synth.thresholds(H, T)
+    ta[0, T // 2] = -np.inf          # one all-on row
+    plan = hs.Plan(T, 0, H, n_chans=LENS)
+    caps = [H * T * n + 8 for n in LENS]
+    (fops, lds, tat, out, offs_d, caps_d, counts), offs = batched_call(plan, devs, ta, caps)
+    res = unpack_batched(out, counts, offs, caps)
+    s_row, s_bin = plan.info["s_row"], plan.info["s_bin"]
+    for f, n in enumerate(LENS):
+        gi, gp, gc = res[f]
+        want, wc = oracle_triples(stores[f], H, ta)
+        assert np.array_equal(gc, wc), (f, gc, wc)
+        assert np.array_equal(triples(gi, gp, s_row, s_bin), want), f
+        single = hs.Plan(T, n, H)
+        si, sp, sc = gpu_detect(single, devs[f], ta, capacity=caps[f])
+        assert np.array_equal(sc, gc)
+        assert np.array_equal(triples(si, sp, single.info["s_row"], single.info["s_bin"]), want)
+
+
+def test_batched_small_capacity_counts_exact():
+    H, T = 8, 21
+    devs, stores = make_batch(LENS, T, H, 8100)
+    ta = synth.thresholds(H, T)
+    plan = hs.Plan(T, 0, H, n_chans=LENS)
+    caps = [5] * len(LENS)
+    (_, _, _, out, _, _, counts), offs = batched_call(plan, devs, ta, caps)
+    res = unpack_batched(out, counts, offs, caps)
+    for f in range(len(LENS)):
+        want, wc = oracle_triples(stores[f], H, ta)
+        gi, gp, gc = res[f]
+        assert np.array_equal(gc, wc)
+        assert len(gi) == min(5, int(wc[-1]))
+        got = triples(gi, gp, plan.info["s_row"], plan.info["s_bin"])
+        wset = set(map(tuple, want))
+        assert all(tuple(t) in wset for t in got)
+
+
+@pytest.mark.parametrize("dtype", [torch.float16, torch.bfloat16])
+def test_batched_reduced_precision(dtype):
+    H, T = 8, 85
+    lens = [5000, 777, 65536]
+    devs, stores = make_batch(lens, T, H, 8200, dtype=dtype, scale=0.125)
+    ta = synth.thresholds(H, T)
+    name = "f16" if dtype == torch.float16 else "bf16"
+    plan = hs.Plan(T, 0, H, dtype=name, input_scale=0.125, n_chans=lens)
+    caps = [20000] * len(lens)
+    (_, _, _, out, _, _, counts), offs = batched_call(plan, devs, ta, caps)
+    res = unpack_batched(out, counts, offs, caps)
+    for f in range(len(lens)):
+        want, wc = oracle_triples(stores[f], H, ta, scale=0.125)
+        gi, gp, gc = res[f]
+        assert np.array_equal(gc, wc)
+        assert np.array_equal(triples(gi, gp, plan.info["s_row"], plan.info["s_bin"]), want)
+
+
+def test_batched_graph_replay():
+    """Capture counter clear + persistent kernel in a HIP graph; every replay
+    (with eager work and synchronisation in between) equals the eager call."""
+    H, T = 16, 85
+    lens = [65536, 4096, 30000, 1000]
+    devs, _ = make_batch(lens, T, H, 8300)
+    ta = synth.thresholds(H, T)
+    plan = hs.Plan(T, 0, H, n_chans=lens)
+    caps = [200000] * len(lens)
+    args, offs = batched_call(plan, devs, ta, caps)      # eager (uploads the plan tables)
+    fops, lds, tat, out, offs_d, caps_d, counts = args
+    ref = [(triples(i, p, plan.info["s_row"], plan.info["s_bin"]), c)
+           for i, p, c in unpack_batched(out, counts, offs, caps)]
+    s = torch.cuda.Stream()
+    g = torch.cuda.CUDAGraph()
+    torch.cuda.synchronize()
+    with torch.cuda.graph(g, stream=s):
+        hs.hs_detect_batched(plan.handle, fops, lds, tat, out, offs_d, caps_d, counts, stream=s)
+    for rep in range(4):
+        out.fill_(-1)
+        counts.fill_(12345)
+        junk = torch.randn(1 << 20, device="cuda").sum()      # eager work between replays
+        g.replay()
+        torch.cuda.synchronize()
+        got = unpack_batched(out, counts, offs, caps)
+        for f in range(len(lens)):
+            gi, gp, gc = got[f]
+            assert np.array_equal(gc, ref[f][1]), (rep, f)
+            assert np.array_equal(triples(gi, gp, plan.info["s_row"], plan.info["s_bin"]),
+                                  ref[f][0]), (rep, f)
+        del junk

@@ -136,3 +136,27 @@ def test_repeat_calls_deterministic_sets():
     a = gpu_detect(plan, dev, ta)
     b = gpu_detect(plan, dev, ta)
     assert_same_candidates(a, (np.sort(b[0]), b[1][np.argsort(b[0])], b[2]))
+
+
+def test_ska_full_size():
+    """The bench workload at full size (85 x 2^21, 8 planes, 50 signals, the
+    launch configuration the benchmark times): every candidate, bitwise."""
+    x = synth.make_ska()
+    H, T = 8, x.shape[0]
+    ta = synth.thresholds(H, T)
+    dev = x.to("cuda")
+    plan = hs.Plan(T, x.shape[1], H)
+    got = gpu_detect(plan, dev, ta, capacity=1 << 22)
+    want = oracle_detect_sorted(x, H, ta, nthreads=16)
+    assert_same_candidates(got, want)
+    assert 250000 < got[2][-1] < 350000
+
+
+def test_large_ragged_h16():
+    T, N, H = 85, (1 << 20) + 77, 16
+    x = exp_plane(T, N, 31)
+    ta = synth.thresholds(H, T)
+    dev, store = padded_device(x)
+    plan = hs.Plan(T, N, H)
+    got = gpu_detect(plan, dev, ta, capacity=1 << 22)
+    assert_same_candidates(got, oracle_detect_sorted(store, H, ta, nthreads=16))

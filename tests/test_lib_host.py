@@ -50,8 +50,9 @@ def test_plan_ska_geometry():
     assert info["src_rows"][1:9] == [85, 43, 29, 22, 18, 15, 13, 12]
     assert sum(info["src_rows"][1:9]) == 237
     assert (info["s_row"], info["s_k"], info["s_bin"]) == (24, 3, 21)
-    assert info["tile_rows"] == 85 and info["row_blocks"] == 1
-    assert info["tiles_total"] == (1 << 21) // info["tile_bins"]
+    # two row blocks: template indices -42..0 and 1..42 (disjoint source rows)
+    assert info["tile_rows"] == 43 and info["row_blocks"] == 2
+    assert info["tiles_total"] == 2 * (1 << 21) // info["tile_bins"]
     # staged words per full tile ~ sum_m rows_m * B/m: 0.54x of the tile's own points
     ratio = info["staged_words"] / (85 * info["tile_bins"])
     assert 0.53 < ratio < 0.56
@@ -74,7 +75,8 @@ def test_plan_batched_tiles():
     lens = [1 << 19, 1 << 20, 1 << 21, 1000, 1]
     p = hs.Plan(85, 0, 16, n_chans=lens)
     tb = p.info["tile_bins"]
-    assert p.info["tiles_total"] == sum((n + tb - 1) // tb for n in lens)
+    rb = p.info["row_blocks"]
+    assert p.info["tiles_total"] == rb * sum((n + tb - 1) // tb for n in lens)
     assert p.info["n_chan_max"] == 1 << 21
 
 
@@ -93,6 +95,11 @@ def test_plan_rejects_bad_shapes(kw):
     with pytest.raises(hs.HsError) as e:
         hs.Plan(**kw)
     assert e.value.status == hs.HS_ERR_INVALID
+
+
+def test_plan_rejects_scaled_fp32():
+    with pytest.raises(hs.HsError):
+        hs.Plan(85, 1000, 8, dtype="f32", input_scale=0.5)
 
 
 def test_plan_accepts_limits():
