@@ -8,7 +8,7 @@ and the helpers at the bottom are conveniences over the same calls.
 
 The library must be built in-tree first::
 
-    python -m paper_1805_12258_amd.build
+    python paper_1805_12258_amd/build.py
 
 Importing this package raises ``ImportError`` when it is not.  torch is
 imported before the library is opened so that both use the same HIP runtime.
@@ -22,7 +22,7 @@ _PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_PKG, "libhs.so")
 
 if not os.path.exists(LIB_PATH):
-    raise ImportError("libhs.so is not built; run `python -m paper_1805_12258_amd.build` "
+    raise ImportError("libhs.so is not built; run `python paper_1805_12258_amd/build.py` "
                       "(there is no CPU fallback)")
 
 _lib = ctypes.CDLL(LIB_PATH)
@@ -243,7 +243,10 @@ class Plan:
     def __del__(self):
         h = getattr(self, "handle", None)
         if h is not None and h.value:
-            _c_hs_plan_destroy(h)
+            try:
+                _c_hs_plan_destroy(h)
+            except TypeError:          # interpreter shutdown: module globals are gone
+                pass
             self.handle = None
 
     def _fop(self, fop):

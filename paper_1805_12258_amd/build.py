@@ -1,6 +1,9 @@
 """Build libhs.so (HIP for gfx950) in-tree with hipcc.
 
-    python -m paper_1805_12258_amd.build [--force] [--jobs N]
+    python paper_1805_12258_amd/build.py [--force] [--jobs N]
+
+Run it by path: it needs only the standard library, while importing the
+package requires the built library.
 
 Every HIP translation unit is compiled for gfx950 only, with -ffp-contract=off
 (sums must round exactly as the sequential fp32 recursion) and with packed

@@ -38,6 +38,9 @@ bool fop_ok(const hs_plan* p, const void* fop, int64_t ld, int64_t N)
 {
     if (!fop || ld < N) return false;
     if (reinterpret_cast<uintptr_t>(fop) & 15) return false;
+    // the staging addresses source words by 32-bit offsets within the source
+    // rows of one stretch factor (at most R/2 + 2 rows)
+    if (ld * (int64_t)(p->tile_rows / 2 + 2) + hsk::kTileBins >= ((int64_t)1 << 32)) return false;
     return ld % ld_align(p->dtype) == 0;
 }
 
@@ -56,35 +59,17 @@ hsk::TileArgs tile_args(const hs_plan* p, const void* fop, int64_t ld)
     a.s_row = p->s_row;
     a.s_bin = p->s_bin;
     a.kmask = (1u << p->s_k) - 1u;
+    a.table_whole = hsk::table_whole((int)p->T, p->H) ? 1 : 0;
     return a;
 }
 
 int64_t bin_tiles(int64_t n) { return (n + hsk::kTileBins - 1) / hsk::kTileBins; }
 
-// Compute units of the current device (cached per device).
-int cu_count()
-{
-    static int cache[64] = {0};
-    int dev = 0;
-    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 256;
-    if (!cache[dev]) {
-        int n = 0;
-        if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || n < 1)
-            n = 256;
-        cache[dev] = n;
-    }
-    return cache[dev];
-}
-
-// Persistent grid: blocks that fit the compute units at once.
+// Persistent grid override (0: the launcher sizes the grid from occupancy).
 int persistent_grid(const hs_plan* p, int64_t tiles)
 {
-    int per_cu = (160 * 1024) / p->lds_bytes;
-    if (per_cu > 2048 / hsk::kThreads) per_cu = 2048 / hsk::kThreads;
-    if (per_cu < 1) per_cu = 1;
-    int64_t g = p->persistent_blocks > 0 ? p->persistent_blocks : (int64_t)cu_count() * per_cu;
-    if (g > tiles) g = tiles;
-    return (int)(g < 1 ? 1 : g);
+    (void)tiles;
+    return p->persistent_blocks;
 }
 
 }  // namespace
@@ -137,22 +122,26 @@ hs_status hs_plan_create(hs_plan** out, const hs_plan_desc* d)
         // indices and the non-negative ones in different tiles, which stage
         // disjoint source rows (floor keeps the sign).
         int R;
+        auto fits = [&](int r) {
+            // two blocks per compute unit; the two staging buffers are
+            // addressed by LDS-DMA through M0 and stay below 64 KiB
+            return hsk::fused_lds_bytes((int)p->T, r, p->H, hsk::kModeDetect) <= kLdsBudget &&
+                   2 * hsk::fused_stage_words((int)p->T, r, p->H) * 4 <= 65536;
+        };
         if (d->tile_rows > 0) {
             R = (int)std::min<int64_t>(d->tile_rows, p->T);
         } else {
-            const int64_t blocks = (p->T + hsk::kMaxTileRows - 1) / hsk::kMaxTileRows;
+            int64_t blocks = (p->T + hsk::kMaxTileRows - 1) / hsk::kMaxTileRows;
             R = (int)((p->T + blocks - 1) / blocks);
+            while (R > 1 && !fits(R)) {
+                ++blocks;
+                R = (int)((p->T + blocks - 1) / blocks);
+            }
         }
-        if (R > hsk::kMaxTileRows) { delete p; return HS_ERR_UNSUPPORTED; }
+        if (R > hsk::kMaxTileRows || !fits(R)) { delete p; return HS_ERR_UNSUPPORTED; }
         p->tile_rows = R;
         p->row_blocks = (int)((p->T + R - 1) / R);
         p->lds_bytes = hsk::fused_lds_bytes((int)p->T, R, p->H, hsk::kModeDetect);
-        // the staged region is addressed by LDS-DMA through M0: keep it below
-        // 64 KiB; two blocks must fit one compute unit's 160 KiB
-        if (p->lds_bytes > kLdsBudget || hsk::fused_stage_words((int)p->T, R, p->H) * 4 > 65536) {
-            delete p;
-            return HS_ERR_UNSUPPORTED;
-        }
 
         if (d->n_fops == 0) {
             p->tiles_total = p->row_blocks * bin_tiles(p->N);
@@ -309,6 +298,7 @@ hs_status hs_detect_batched(const hs_plan* p, const void* const* fops, const int
         b.s_row = p->s_row;
         b.s_bin = p->s_bin;
         b.kmask = (1u << p->s_k) - 1u;
+        b.table_whole = hsk::table_whole((int)p->T, p->H) ? 1 : 0;
         const int grid = persistent_grid(p, p->tiles_total);
         return from_hip(hsk::launch_batched(p->dtype, p->H, b, grid, p->lds_bytes, s));
     } catch (...) {

@@ -31,6 +31,7 @@ int fused_stage_words(int T, int R, int H)
             const int nrow = (int)(floordiv(r1 - 1 - c, m) - floordiv(r0 - c, m) + 1);
             tot += nrow * stage_pitch(m);
         }
+        tot = (tot + 3) & ~3;      // the row table after it is read as float4
         if (tot > worst) worst = tot;
     }
     return worst;
@@ -39,7 +40,7 @@ int fused_stage_words(int T, int R, int H)
 int fused_lds_bytes(int T, int R, int H, int mode)
 {
     (void)mode;
-    return fused_stage_words(T, R, H) * 4 + smem_tail_bytes(R, H);
+    return 2 * fused_stage_words(T, R, H) * 4 + smem_tail_bytes(T, R, H);
 }
 
 hipError_t launch_fused(int mode, int dtype, int H, const TileArgs& a, int64_t n_tiles, int grid,

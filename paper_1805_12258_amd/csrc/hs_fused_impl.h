@@ -94,20 +94,28 @@ __device__ __forceinline__ void static_for(F&& f)
     }
 }
 
-// Shared-memory carve-up of one block.
+// Shared-memory carve-up of one block.  The staging buffer and (when it
+// covers only one tile) the row table are double-buffered: the loads of the
+// next tile land in one copy while the current tile is summed from the other.
 struct Smem {
-    float* stage;                 // staged source rows, all m >= 2
+    float* stage[2];              // staged source rows of all m >= 2
+    float* rowtab[2];             // per row: staged-row offsets of m = 2..H, then
+                                  // the H thresholds (both entries alias when the
+                                  // table covers the whole plane)
     uint2* cand;                  // [kWaves][kWaveCandCap] per-wave candidate buffers
     int* cnt;                     // [kMaxH] per-plane counts of the block
 };
 
-__device__ __forceinline__ Smem carve(float* lds, int stage_words, int R, int H)
+__device__ __forceinline__ Smem carve(float* lds, int stage_words, int T, int R, int H,
+                                      bool whole)
 {
     Smem s;
-    (void)R;
-    (void)H;
-    s.stage = lds;
-    s.cand = reinterpret_cast<uint2*>(lds + stage_words);
+    s.stage[0] = lds;
+    s.stage[1] = lds + stage_words;
+    s.rowtab[0] = lds + 2 * stage_words;
+    const int trows = whole ? T : R;
+    s.rowtab[1] = whole ? s.rowtab[0] : s.rowtab[0] + trows * row_table_stride(H);
+    s.cand = reinterpret_cast<uint2*>(s.rowtab[1] + trows * row_table_stride(H));
     s.cnt = reinterpret_cast<int*>(s.cand + kWaves * kWaveCandCap);
     return s;
 }
@@ -128,7 +136,7 @@ __device__ __forceinline__ uint64_t read_first_u64(uint64_t x)
 // Write a wave's buffered candidates to global memory (one atomic per wave)
 // and count them per plane in the block's LDS counters (the plane is read
 // back from each candidate word).
-__device__ __forceinline__ void flush_wave(const uint2* wbuf, int n, hs_cand* out, int64_t cap,
+__device__ __noinline__ void flush_wave(const uint2* wbuf, int n, hs_cand* out, int64_t cap,
                                            unsigned long long* total, int* block_cnt, int s_bin,
                                            uint32_t kmask)
 {
@@ -157,127 +165,208 @@ __device__ __forceinline__ void flush_counts(const Smem& sh, unsigned long long*
     __syncthreads();
 }
 
-// One tile: stage, form the planes, detect or store.  Starts and ends with a
-// barrier so the staging buffer is free when it is refilled.
+// Append the hits of one (row, plane) to the wave's LDS buffer.  Called by
+// the whole wave (uniform control flow): positions come from wave ballots.
+template <int V, int H>
+__device__ __forceinline__ void emit_hits(const float* acc, float t, int r, int k, int64_t jb,
+                                          const TileArgs& a, const Smem& sh, WaveState<H>& ws,
+                                          uint2* wbuf)
+{
+    const uint32_t hi = (uint32_t)(((uint64_t)r << a.s_row) | ((uint64_t)(k - 1) << a.s_bin));
+#pragma unroll
+    for (int v = 0; v < V; ++v) {
+        const bool hit = acc[v] > t;
+        const uint64_t mk = __builtin_amdgcn_ballot_w64(hit);
+        if (mk) {
+            if (hit) {
+                const int pos = ws.n + (int)__builtin_amdgcn_mbcnt_hi(
+                    (uint32_t)(mk >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mk, 0));
+                wbuf[pos] = make_uint2(hi | (uint32_t)(jb + v), __float_as_uint(acc[v]));
+            }
+            ws.n += __builtin_popcountll(mk);
+        }
+    }
+}
+
+// Geometry of one row block (constant while a block walks the bin tiles of
+// that row block): source rows and staging layout of every stretch factor.
+template <int H>
+struct RowGeo {
+    int rb, r0, nr;
+    int a_lo[H + 1], nrow[H + 1], offm[H + 1];
+};
+
+template <int H>
+__device__ __forceinline__ void row_geo(const TileArgs& a, int rb, RowGeo<H>& g)
+{
+    g.rb = rb;
+    g.r0 = rb * a.R;
+    const int r1 = min(g.r0 + a.R, a.T);
+    g.nr = r1 - g.r0;
+    const int i_lo = g.r0 - a.c, i_hi = r1 - 1 - a.c;
+    int tot = 0;
+#pragma unroll
+    for (int m = 2; m <= H; ++m) {
+        g.a_lo[m] = floordiv32(i_lo, m);
+        g.nrow[m] = floordiv32(i_hi, m) - g.a_lo[m] + 1;
+        g.offm[m] = tot;
+        tot += g.nrow[m] * stage_pitch(m);
+    }
+}
+
+// Start every load of tile (g.rb, bt): the shrunken source ranges into the
+// staging buffer `stage` (LDS-DMA for fp32), the m = 1 values of the wave's
+// rows into `x`, and (when the row table does not cover the whole plane) the
+// tile's row table into `rowtab`.  Nothing is waited for here.
 template <typename TIn, int H, int MODE>
-__device__ __forceinline__ void run_tile(const TileArgs& a, int64_t tile, const Smem& sh,
-                                         WaveState<H>& ws)
+__device__ __forceinline__ void issue_tile(const TileArgs& a, const RowGeo<H>& g, int bt,
+                                           float* stage, float* rowtab,
+                                           float (&x)[kRowsPerWave][kV])
 {
     using Ld = Io<TIn>;
     using T = typename Ld::T;
     const T* __restrict__ fop = reinterpret_cast<const T*>(a.fop);
-    // thresholds are read-only for the whole launch: read them through the
-    // constant address space so uniform reads become scalar loads
-    const __attribute__((address_space(4))) float* ta =
-        (const __attribute__((address_space(4))) float*)a.ta;
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-
-    const int rb = (int)(tile % a.row_blocks);
-    const int64_t j0 = (tile / a.row_blocks) * kTileBins;
-    const int r0 = rb * a.R;
-    const int r1 = min(r0 + a.R, a.T);
-    const int nr = r1 - r0;
-    const int c = a.c;
-    const int64_t N = a.N;
+    const int N = (int)a.N;
+    // Bin arithmetic is 32-bit (N < 2^31): scalar 64-bit division would cost
+    // more than the tile's whole row loop.
+    const int j0 = bt * kTileBins;
+    // In a full tile every staged word up to the pitch lies inside the plane
+    // (floor(j0/m) + pitch(m) <= N for m >= 2), so only the last chunk of a
+    // region needs a mask; the partial last tile checks each column.
+    const bool full = j0 + kTileBins <= N;
     const int64_t ld = a.ld;
-    const int i_lo = r0 - c, i_hi = r1 - 1 - c;
-    const int64_t jend = min(j0 + (int64_t)kTileBins, N);   // one past the tile's last bin
+    const uint32_t ld32 = (uint32_t)ld;
 
-    // Source ranges of every stretch factor (scalar).
-    int a_lo[H + 1], nrow[H + 1], offm[H + 1], span[H + 1];
-    int64_t blo[H + 1];
-    int tot = 0;
+    // 1. Source ranges.  Region m holds nrow[m] rows of stage_pitch(m) words
+    // back to back; every wave instruction fills 64 consecutive words, each
+    // lane computing its own source offset.
 #pragma unroll
     for (int m = 2; m <= H; ++m) {
-        a_lo[m] = floordiv32(i_lo, m);
-        nrow[m] = floordiv32(i_hi, m) - a_lo[m] + 1;
-        blo[m] = j0 / m;
-        span[m] = (int)((jend - 1) / m - blo[m] + 1);
-        offm[m] = tot;
-        tot += nrow[m] * stage_pitch(m);
-    }
-
-    __syncthreads();   // the previous tile is done with the staging buffer
-
-    // 1. Stage the shrunken source ranges (this wave's rows of each region).
-#pragma unroll
-    for (int m = 2; m <= H; ++m) {
-        for (int row = wave; row < nrow[m]; row += kWaves) {
-            const T* src = fop + (int64_t)(a_lo[m] + row + c) * ld + blo[m];
-            float* dst = sh.stage + offm[m] + row * stage_pitch(m);
-            for (int ch = 0; ch * 64 < span[m]; ++ch) {
-                const int col = ch * 64 + lane;
+        const int P = stage_pitch(m);
+        const int words = g.nrow[m] * P;
+        const int nchunk = (words + 63) >> 6;
+        const int blo = (int)((uint32_t)j0 / (uint32_t)m);
+        const int span = full ? P : (int)((uint32_t)(min(j0 + kTileBins, N) - 1) / (uint32_t)m) - blo + 1;
+        const T* base = fop + (int64_t)(g.a_lo[m] + a.c) * ld + blo;   // first source word
+        for (int ch = wave; ch < nchunk; ch += kWaves) {
+            const uint32_t e = ((uint32_t)ch << 6) + lane;
+            const uint32_t row = e / (uint32_t)P;
+            const uint32_t col = e - row * (uint32_t)P;
+            if (e < (uint32_t)words && (full || col < (uint32_t)span)) {
+                const T* src = base + (row * ld32 + col);
                 if constexpr (sizeof(T) == 4) {
-                    if (col < span[m]) {
-                        __builtin_amdgcn_global_load_lds(src + col, (lds_ptr_t)(dst + ch * 64), 4, 0, 0);
-                    }
+                    __builtin_amdgcn_global_load_lds(src, (lds_ptr_t)(stage + g.offm[m] + (ch << 6)), 4, 0, 0);
                 } else {
-                    if (col < span[m]) dst[col] = Ld::one(src + col) * a.inv_scale;
+                    stage[g.offm[m] + e] = Ld::one(src) * a.inv_scale;
                 }
             }
         }
     }
 
     // 2. The m = 1 values of every row this wave owns.
-    const int64_t jb = j0 + kV * lane;
-    bool valid[kV];
-#pragma unroll
-    for (int v = 0; v < kV; ++v) valid[v] = jb + v < N;
-    const bool tile_full = j0 + kTileBins <= N;        // wave-uniform
-    float x[kRowsPerWave][kV];
-    if (tile_full) {
+    const int jb = j0 + kV * lane;
+    if (full) {
+        // unconditional loads (rows past the tile re-read its last row and
+        // are ignored) land straight in their registers, so nothing waits
+        // for them before the tile is summed
 #pragma unroll
         for (int q = 0; q < kRowsPerWave; ++q) {
-            const int rr = wave + kWaves * q;
-            if (rr < nr) Ld::four(fop + (int64_t)(r0 + rr) * ld + jb, x[q]);
+            const int rr = min(wave + kWaves * q, g.nr - 1);
+            Ld::four(fop + (int64_t)(g.r0 + rr) * ld + jb, x[q]);
         }
     } else {
 #pragma unroll
         for (int q = 0; q < kRowsPerWave; ++q) {
             const int rr = wave + kWaves * q;
-            const T* p = fop + (int64_t)(r0 + rr) * ld + jb;
-#pragma unroll
+            const T* p = fop + (int64_t)(g.r0 + rr) * ld + jb;
             // bins past the end start at -inf: no sum of them can pass a
             // threshold (-inf + x is -inf or NaN)
+#pragma unroll
             for (int v = 0; v < kV; ++v)
-                x[q][v] = (rr < nr && valid[v]) ? Ld::one(p + v) : -__builtin_inff();
+                x[q][v] = (rr < g.nr && jb + v < N) ? Ld::one(p + v) : -__builtin_inff();
         }
     }
 
-    // Per-lane view of the staged rows.
+    // 3. Row table of the tile (large planes only): per tile row, where each
+    // stretch factor's source row sits in the staging buffer, and the row's
+    // thresholds.  Per-row scalar work would otherwise dominate the row loop.
+    if (!a.table_whole) {
+        constexpr int RS = row_table_stride(H);
+        constexpr int SO = row_table_thr_offset(H);
+        for (int e = threadIdx.x; e < g.nr * RS; e += kThreads) {
+            const int rr = e / RS, col = e - rr * RS;
+            const int i = g.r0 + rr - a.c;
+            float val = 0.0f;
+            if (col < H - 1) {
+                int off = 0;
+#pragma unroll
+                for (int m = 2; m <= H; ++m)
+                    if (col == m - 2) off = g.offm[m] + (floordiv32(i, m) - g.a_lo[m]) * stage_pitch(m);
+                val = __int_as_float(off);
+            } else if (MODE == kModeDetect && col >= SO && col < SO + H) {
+                // thresholds exist only in the detection mode (a.ta is null otherwise)
+                val = a.ta[(int64_t)(col - SO) * a.T + g.r0 + rr];
+            }
+            rowtab[e] = val;
+        }
+    }
+}
+
+// Form the planes of one tile whose loads have completed (after a barrier):
+// HP_k for k = 1..H in the order of Eq. 2, detected or stored.
+template <typename TIn, int H, int MODE>
+__device__ __forceinline__ void compute_tile(const TileArgs& a, const RowGeo<H>& g, int bt,
+                                             const Smem& sh, const float* stage,
+                                             const float* rowtab,
+                                             const float (&x)[kRowsPerWave][kV], WaveState<H>& ws)
+{
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int j0 = bt * kTileBins;
+    const int r0 = g.r0;
+    const int nr = g.nr;
+    const int N = (int)a.N;
+    const int jb = j0 + kV * lane;
+    const bool tile_full = j0 + kTileBins <= N;        // wave-uniform
+    constexpr int RS = row_table_stride(H);
+    constexpr int SO = row_table_thr_offset(H);
+    const int trow0 = a.table_whole ? r0 : 0;          // table row of tile row 0
+
+    // Per-lane view of the staged rows: the lane's first source word of each
+    // stretch factor and where its kV bins cross to the next word.
     int loff[H + 1], sig[H + 1];
 #pragma unroll
     for (int m = 2; m <= H; ++m) {
-        const int rho = (int)(j0 - blo[m] * m);       // j0 mod m
-        const int t = rho + kV * lane;
-        loff[m] = offm[m] + t / m;
+        const int blo = (int)((uint32_t)j0 / (uint32_t)m);
+        const int t = (j0 - blo * m) + kV * lane;     // (j0 mod m) + kV * lane
+        loff[m] = t / m;
         sig[m] = t % m;
     }
 
-    __builtin_amdgcn_s_waitcnt(0);
-    __syncthreads();
-
     uint2* wbuf = sh.cand + wave * kWaveCandCap;
+    // rows unrolled with static register indices (a dynamic index into the
+    // prefetched rows would make every load complete before the tile starts)
 #pragma unroll
     for (int q = 0; q < kRowsPerWave; ++q) {
         const int rr = wave + kWaves * q;
         if (rr >= nr) break;
         const int r = r0 + rr;
-        const int i = r - c;
-        // All LDS reads of the row first (thresholds and staged source
-        // words), so their latencies overlap; the candidate writes below
-        // could otherwise alias them and serialise every read.
-        float thr[H];
-        if constexpr (MODE == kModeDetect) {
+        // All LDS reads of the row first (row table and staged source words),
+        // so their latencies overlap; the candidate writes below could
+        // otherwise alias them and serialise every read.
+        const float* rt = rowtab + (trow0 + rr) * RS;
+        float tab[RS];
 #pragma unroll
-            for (int k = 0; k < H; ++k) thr[k] = ta[k * a.T + r];
+        for (int u = 0; u < RS / 4; ++u) {
+            const float4 q4 = reinterpret_cast<const float4*>(rt)[u];
+            tab[4 * u] = q4.x; tab[4 * u + 1] = q4.y; tab[4 * u + 2] = q4.z; tab[4 * u + 3] = q4.w;
         }
         float w[H + 1][2];
         static_for<2, H>([&](auto mc) {
             constexpr int m = decltype(mc)::value;
-            const int srow = floordiv32(i, m) - a_lo[m];
-            const float* p = sh.stage + loff[m] + srow * stage_pitch(m);
+            const float* p = stage + loff[m] + __float_as_int(tab[m - 2]);
             if constexpr (kV % m == 0) {
 #pragma unroll
                 for (int u = 0; u < kV / m; ++u) w[m][u] = p[u];
@@ -295,45 +384,26 @@ __device__ __forceinline__ void run_tile(const TileArgs& a, int64_t tile, const 
 
         auto emit = [&](int k) {
             if constexpr (MODE == kModeDetect) {
-                const float t = thr[k - 1];
-                bool hit[kV];
-                uint64_t mk[kV];
-                uint64_t mall = 0;
-#pragma unroll
-                for (int v = 0; v < kV; ++v) {
-                    hit[v] = acc[v] > t;
-                    mk[v] = __builtin_amdgcn_ballot_w64(hit[v]);
-                    mall |= mk[v];
-                }
-                if (mall) {
+                const float t = tab[SO + k - 1];
+                // cheap wave test first: the largest of the lane's kV sums
+                // (NaN operands are ignored by max and fail the compare)
+                const float mx = fmaxf(fmaxf(acc[0], acc[1]), fmaxf(acc[2], acc[3]));
+                if (__builtin_expect(__builtin_amdgcn_ballot_w64(mx > t) != 0, 0)) {
                     // room for every hit of this (row, plane): at most kV per lane
                     if (ws.n > kWaveCandCap - kV * 64) {
                         flush_wave(wbuf, ws.n, a.out, a.cap, &a.counts[H], sh.cnt, a.s_bin, a.kmask);
                         ws.n = 0;
                     }
-                    const uint32_t hi =
-                        (uint32_t)(((uint64_t)r << a.s_row) | ((uint64_t)(k - 1) << a.s_bin));
-#pragma unroll
-                    for (int v = 0; v < kV; ++v) {
-                        if (mk[v]) {
-                            if (hit[v]) {
-                                const int pos = ws.n + (int)__builtin_amdgcn_mbcnt_hi(
-                                    (uint32_t)(mk[v] >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mk[v], 0));
-                                wbuf[pos] = make_uint2(hi | (uint32_t)(jb + v), __float_as_uint(acc[v]));
-                            }
-                            ws.n += __builtin_popcountll(mk[v]);
-                        }
-                    }
+                    emit_hits<kV, H>(acc, t, r, k, jb, a, sh, ws, wbuf);
                 }
             } else {
                 float* dst = a.hp + ((int64_t)(k - 1) * a.T + r) * N + jb;
-                const float* y = acc;
                 if (tile_full && (N & 3) == 0) {
-                    *reinterpret_cast<float4*>(dst) = make_float4(y[0], y[1], y[2], y[3]);
+                    *reinterpret_cast<float4*>(dst) = make_float4(acc[0], acc[1], acc[2], acc[3]);
                 } else {
 #pragma unroll
                     for (int v = 0; v < kV; ++v)
-                        if (valid[v]) dst[v] = y[v];
+                        if (jb + v < N) dst[v] = acc[v];
                 }
             }
         };
@@ -364,6 +434,75 @@ __device__ __forceinline__ void run_tile(const TileArgs& a, int64_t tile, const 
     }
 }
 
+// Tiles [begin, end) of a contiguous run in row-block-major order (tile
+// t = rb * n_bt + bt), processed with the loads of tile t+1 in flight while
+// tile t is summed.  The two halves of the loop body use the two buffers with
+// static register indices, so no wait on the in-flight loads is implied.
+template <typename TIn, int H, int MODE>
+__device__ __forceinline__ void run_tiles(const TileArgs& a, int64_t begin, int64_t end, int n_bt,
+                                          const Smem& sh, WaveState<H>& ws)
+{
+    if (begin >= end) return;
+    float xa[kRowsPerWave][kV], xb[kRowsPerWave][kV];
+    int rb = (int)(begin / n_bt);
+    int bt = (int)(begin - (int64_t)rb * n_bt);
+    RowGeo<H> gc, gn;                 // row geometry of the current / next tile
+    row_geo<H>(a, rb, gc);
+    gn = gc;
+    __syncthreads();   // the previous run is done with both buffers
+    issue_tile<TIn, H, MODE>(a, gc, bt, sh.stage[0], sh.rowtab[0], xa);
+    int64_t t = begin;
+    for (;;) {
+        int bt1 = bt + 1;
+        if (bt1 == n_bt) { bt1 = 0; row_geo<H>(a, gc.rb + 1, gn); }
+        __builtin_amdgcn_s_waitcnt(0);
+        __syncthreads();
+        if (t + 1 < end) issue_tile<TIn, H, MODE>(a, gn, bt1, sh.stage[1], sh.rowtab[1], xb);
+        compute_tile<TIn, H, MODE>(a, gc, bt, sh, sh.stage[0], sh.rowtab[0], xa, ws);
+        gc = gn; bt = bt1;
+        if (++t >= end) break;
+
+        bt1 = bt + 1;
+        if (bt1 == n_bt) { bt1 = 0; row_geo<H>(a, gc.rb + 1, gn); }
+        __builtin_amdgcn_s_waitcnt(0);
+        __syncthreads();
+        if (t + 1 < end) issue_tile<TIn, H, MODE>(a, gn, bt1, sh.stage[0], sh.rowtab[0], xa);
+        compute_tile<TIn, H, MODE>(a, gc, bt, sh, sh.stage[1], sh.rowtab[1], xb, ws);
+        gc = gn; bt = bt1;
+        if (++t >= end) break;
+    }
+}
+
+// Row table for every row of the plane, built once per launch by the whole
+// block: entries of row r refer to the staging layout of r's row block.
+template <int H, int MODE>
+__device__ __forceinline__ void build_whole_table(int T, int R, int c, const float* ta,
+                                                  float* rowtab)
+{
+    constexpr int RS = row_table_stride(H);
+    constexpr int SO = row_table_thr_offset(H);
+    for (int e = threadIdx.x; e < T * RS; e += kThreads) {
+        const int r = e / RS, col = e - r * RS;
+        float val = 0.0f;
+        if (col < H - 1) {
+            const int rb = r / R;
+            const int r0 = rb * R, r1 = min(r0 + R, T);
+            const int i_lo = r0 - c, i_hi = r1 - 1 - c, i = r - c;
+            int off = 0, sel = 0;
+#pragma unroll
+            for (int m = 2; m <= H; ++m) {
+                const int alo = floordiv32(i_lo, m);
+                if (col == m - 2) sel = off + (floordiv32(i, m) - alo) * stage_pitch(m);
+                off += (floordiv32(i_hi, m) - alo + 1) * stage_pitch(m);
+            }
+            val = __int_as_float(sel);
+        } else if (MODE == kModeDetect && col >= SO && col < SO + H) {
+            val = ta[(int64_t)(col - SO) * T + r];
+        }
+        rowtab[e] = val;
+    }
+}
+
 // Tiles [t_begin, t_end) of block b for a grid of g blocks over n tiles.
 __device__ __forceinline__ void block_chunk(int64_t n, int64_t& t_begin, int64_t& t_end)
 {
@@ -373,18 +512,22 @@ __device__ __forceinline__ void block_chunk(int64_t n, int64_t& t_begin, int64_t
     t_end = t_begin + q + (b < r ? 1 : 0);
 }
 
+template <int H> constexpr int fused_min_waves() { return 1; }
+
 template <typename TIn, int H, int MODE>
-__global__ __launch_bounds__(kThreads) void k_fused(TileArgs a, int stage_words, int64_t n_tiles)
+__global__ __launch_bounds__(kThreads, fused_min_waves<H>()) void k_fused(TileArgs a, int stage_words,
+                                                                          int64_t n_tiles)
 {
     extern __shared__ __align__(16) float lds[];
-    const Smem sh = carve(lds, stage_words, a.R, H);
+    const Smem sh = carve(lds, stage_words, a.T, a.R, H, a.table_whole != 0);
     WaveState<H> ws;
     ws.n = 0;
     if (threadIdx.x < kMaxH) sh.cnt[threadIdx.x] = 0;
+    if (a.table_whole) build_whole_table<H, MODE>(a.T, a.R, a.c, a.ta, sh.rowtab[0]);
 
     int64_t t0, t1;
     block_chunk(n_tiles, t0, t1);
-    for (int64_t t = t0; t < t1; ++t) run_tile<TIn, H, MODE>(a, t, sh, ws);
+    run_tiles<TIn, H, MODE>(a, t0, t1, (int)((a.N + kTileBins - 1) / kTileBins), sh, ws);
 
     if constexpr (MODE == kModeDetect) {
         if (ws.n) flush_wave(sh.cand + (threadIdx.x >> 6) * kWaveCandCap, ws.n, a.out, a.cap,
@@ -395,10 +538,10 @@ __global__ __launch_bounds__(kThreads) void k_fused(TileArgs a, int stage_words,
 
 // Batched persistent kernel: the grid walks the tiles of every FOP.
 template <typename TIn, int H>
-__global__ __launch_bounds__(kThreads) void k_batched(BatchArgs b, int stage_words)
+__global__ __launch_bounds__(kThreads, fused_min_waves<H>()) void k_batched(BatchArgs b, int stage_words)
 {
     extern __shared__ __align__(16) float lds[];
-    const Smem sh = carve(lds, stage_words, b.R, H);
+    const Smem sh = carve(lds, stage_words, b.T, b.R, H, b.table_whole != 0);
     WaveState<H> ws;
     ws.n = 0;
     if (threadIdx.x < kMaxH) sh.cnt[threadIdx.x] = 0;
@@ -407,6 +550,7 @@ __global__ __launch_bounds__(kThreads) void k_batched(BatchArgs b, int stage_wor
     int64_t t0, t1;
     block_chunk(b.tiles_total, t0, t1);
     if (t0 >= t1) return;
+    if (b.table_whole) build_whole_table<H, kModeDetect>(b.T, b.R, b.c, b.ta, sh.rowtab[0]);
     // FOP holding tile t0 (binary search over the prefix of tile counts)
     int f;
     {
@@ -436,13 +580,16 @@ __global__ __launch_bounds__(kThreads) void k_batched(BatchArgs b, int stage_wor
         a.s_row = b.s_row;
         a.s_bin = b.s_bin;
         a.kmask = b.kmask;
+        a.table_whole = b.table_whole;
         a.hp = nullptr;
         const bool ok = ((reinterpret_cast<uintptr_t>(a.fop) & 15) == 0) &&
                         (a.ld % align_elems == 0) && a.ld >= a.N;
         if (!ok) {
             if (threadIdx.x == 0 && tf == fb) a.counts[H] = ~0ull;
         } else {
-            for (int64_t t = tf; t < fe; ++t) run_tile<TIn, H, kModeDetect>(a, t - fb, sh, ws);
+            // tiles of this FOP segment, numbered from the FOP's first tile
+            run_tiles<TIn, H, kModeDetect>(a, tf - fb, fe - fb, (int)((a.N + kTileBins - 1) / kTileBins),
+                                           sh, ws);
             if (ws.n) {
                 flush_wave(sh.cand + (threadIdx.x >> 6) * kWaveCandCap, ws.n, a.out, a.cap,
                            &a.counts[H], sh.cnt, a.s_bin, a.kmask);
@@ -454,19 +601,41 @@ __global__ __launch_bounds__(kThreads) void k_batched(BatchArgs b, int stage_wor
     }
 }
 
+// Persistent grid: as many blocks as the device holds at once (occupancy of
+// this kernel at this LDS size), at most one per tile.  A positive `grid`
+// overrides.
+template <typename K>
+static int resident_grid(K kernel, int lds_bytes, int64_t n_tiles, int grid)
+{
+    if (grid <= 0) {
+        int dev = 0, cus = 0, per_cu = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1)
+            cus = 256;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)kernel, kThreads,
+                                                         lds_bytes) != hipSuccess || per_cu < 1)
+            per_cu = 1;
+        grid = cus * per_cu;
+    }
+    if (grid > n_tiles) grid = (int)n_tiles;
+    return grid < 1 ? 1 : grid;
+}
+
 template <typename TIn, int H>
 static hipError_t launch_fused_t(int mode, const TileArgs& a, int64_t n_tiles, int grid,
                                  int lds_bytes, hipStream_t s)
 {
-    const int stage_words = (lds_bytes - smem_tail_bytes(a.R, H)) / 4;
+    const int stage_words = (lds_bytes - smem_tail_bytes(a.T, a.R, H)) / 8;
     if (mode == kModeDetect) {
         auto k = k_fused<TIn, H, kModeDetect>;
         (void)hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, lds_bytes);
-        hipLaunchKernelGGL(k, dim3(grid), dim3(kThreads), lds_bytes, s, a, stage_words, n_tiles);
+        const int g = resident_grid(k, lds_bytes, n_tiles, grid);
+        hipLaunchKernelGGL(k, dim3(g), dim3(kThreads), lds_bytes, s, a, stage_words, n_tiles);
     } else {
         auto k = k_fused<TIn, H, kModeSum>;
         (void)hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, lds_bytes);
-        hipLaunchKernelGGL(k, dim3(grid), dim3(kThreads), lds_bytes, s, a, stage_words, n_tiles);
+        const int g = resident_grid(k, lds_bytes, n_tiles, grid);
+        hipLaunchKernelGGL(k, dim3(g), dim3(kThreads), lds_bytes, s, a, stage_words, n_tiles);
     }
     return hipGetLastError();
 }
@@ -474,10 +643,11 @@ static hipError_t launch_fused_t(int mode, const TileArgs& a, int64_t n_tiles, i
 template <typename TIn, int H>
 static hipError_t launch_batched_t(const BatchArgs& b, int grid, int lds_bytes, hipStream_t s)
 {
-    const int stage_words = (lds_bytes - smem_tail_bytes(b.R, H)) / 4;
+    const int stage_words = (lds_bytes - smem_tail_bytes(b.T, b.R, H)) / 8;
     auto k = k_batched<TIn, H>;
     (void)hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, lds_bytes);
-    hipLaunchKernelGGL(k, dim3(grid), dim3(kThreads), lds_bytes, s, b, stage_words);
+    const int g = resident_grid(k, lds_bytes, b.tiles_total, grid);
+    hipLaunchKernelGGL(k, dim3(g), dim3(kThreads), lds_bytes, s, b, stage_words);
     return hipGetLastError();
 }
 

@@ -20,24 +20,45 @@ constexpr int kV = 4;
 constexpr int kTileBins = kV * kLanes;   // 256
 constexpr int kWaves = 8;
 constexpr int kThreads = kWaves * kLanes;
-constexpr int kRowsPerWave = 6;
+constexpr int kRowsPerWave = 4;
 constexpr int kMaxTileRows = kWaves * kRowsPerWave;   // 48
 constexpr int kWaveCandCap = 320;        // per-wave LDS candidate buffer (>= kV*64 + 64)
 constexpr int kMaxH = 16;
 
 // Words reserved per staged source row of stretch factor m: the largest
-// number of distinct floor(j/m) over kTileBins consecutive bins, rounded up
-// to 4 words so every row starts 16-byte aligned.
+// number of distinct floor(j/m) over kTileBins consecutive bins starting at a
+// multiple of kTileBins (j0 mod m is then a multiple of gcd(kTileBins, m),
+// which for a power-of-two tile width is the lowest set bit of m).  The rows
+// of one stretch factor are stored back to back with this pitch.
+static_assert((kTileBins & (kTileBins - 1)) == 0, "tile width must be a power of two");
 __host__ __device__ constexpr int stage_pitch(int m)
 {
-    return (((kTileBins + m - 2) / m + 1) + 3) & ~3;
+    return (m - (m & -m) + kTileBins - 1) / m + 1;
 }
 
-// LDS bytes after the staged region: the per-wave candidate buffers and the
-// per-plane counters of the block.
-__host__ __device__ constexpr int smem_tail_bytes(int R, int H)
+// Row table of a tile: per tile row, the staging offsets of stretch factors
+// 2..H (padded to 4 words) followed by the H thresholds (padded to 4).
+__host__ __device__ constexpr int row_table_thr_offset(int H) { return ((H - 1) + 3) & ~3; }
+__host__ __device__ constexpr int row_table_stride(int H)
 {
-    return (void)R, (void)H, kWaves * kWaveCandCap * 8 + kMaxH * 4;
+    return row_table_thr_offset(H) + ((H + 3) & ~3);
+}
+
+// The row table covers all T rows (and is built once per launch) when it
+// takes at most this many bytes; otherwise it covers one tile's rows.
+constexpr int kWholeTableBytes = 12 * 1024;
+__host__ __device__ constexpr bool table_whole(int T, int H)
+{
+    return T * row_table_stride(H) * 4 <= kWholeTableBytes;
+}
+
+// LDS bytes after the two staging buffers: the row table (two per-tile
+// copies unless it covers the whole plane), the per-wave candidate buffers
+// and the per-plane counters of the block.
+__host__ __device__ constexpr int smem_tail_bytes(int T, int R, int H)
+{
+    return (table_whole(T, H) ? T : 2 * R) * row_table_stride(H) * 4 +
+           kWaves * kWaveCandCap * 8 + kMaxH * 4;
 }
 
 __host__ __device__ inline int64_t floordiv(int64_t a, int64_t b)
@@ -70,6 +91,7 @@ struct TileArgs {
     unsigned long long* counts;   // [H+1]
     int32_t s_row, s_bin;
     uint32_t kmask;               // (1 << s_k) - 1
+    int32_t table_whole;          // row table covers all T rows (built once)
     // materialised planes
     float* hp;              // [H][T][N]
 };
@@ -91,6 +113,7 @@ struct BatchArgs {
     unsigned long long* counts;   // [n_fops][H+1]
     int32_t s_row, s_bin;
     uint32_t kmask;
+    int32_t table_whole;
 };
 
 enum Mode { kModeDetect = 0, kModeSum = 1 };
