@@ -38,9 +38,10 @@ bool fop_ok(const hs_plan* p, const void* fop, int64_t ld, int64_t N)
 {
     if (!fop || ld < N) return false;
     if (reinterpret_cast<uintptr_t>(fop) & 15) return false;
-    // the staging addresses source words by 32-bit offsets within the source
-    // rows of one stretch factor (at most R/2 + 2 rows)
-    if (ld * (int64_t)(p->tile_rows / 2 + 2) + hsk::kTileBins >= ((int64_t)1 << 32)) return false;
+    // the staging addresses source words by 32-bit byte offsets within the
+    // source rows of one stretch factor (at most stage_rows(2) rows)
+    if ((ld * hsk::stage_rows(2) + hsk::kTileBins) * elem_bytes(p->dtype) >= ((int64_t)1 << 32))
+        return false;
     return ld % ld_align(p->dtype) == 0;
 }
 
@@ -117,28 +118,14 @@ hs_status hs_plan_create(hs_plan** out, const hs_plan_desc* d)
         if (p->s_bin + p->s_k + s_r > 32) { delete p; return HS_ERR_INVALID; }
         p->s_row = p->s_bin + p->s_k;
 
-        // Rows per tile: at most kMaxTileRows, the row blocks as even as
-        // possible.  For an odd plane height this puts the negative template
-        // indices and the non-negative ones in different tiles, which stage
-        // disjoint source rows (floor keeps the sign).
-        int R;
-        auto fits = [&](int r) {
-            // two blocks per compute unit; the two staging buffers are
-            // addressed by LDS-DMA through M0 and stay below 64 KiB
-            return hsk::fused_lds_bytes((int)p->T, r, p->H, hsk::kModeDetect) <= kLdsBudget &&
-                   2 * hsk::fused_stage_words((int)p->T, r, p->H) * 4 <= 65536;
-        };
-        if (d->tile_rows > 0) {
-            R = (int)std::min<int64_t>(d->tile_rows, p->T);
-        } else {
-            int64_t blocks = (p->T + hsk::kMaxTileRows - 1) / hsk::kMaxTileRows;
-            R = (int)((p->T + blocks - 1) / blocks);
-            while (R > 1 && !fits(R)) {
-                ++blocks;
-                R = (int)((p->T + blocks - 1) / blocks);
-            }
+        // Rows per tile: kMaxTileRows (the staging layout is sized for it;
+        // the last row block may be shorter), or fewer on request.
+        int R = (int)std::min<int64_t>(d->tile_rows > 0 ? d->tile_rows : hsk::kMaxTileRows, p->T);
+        if (R > hsk::kMaxTileRows ||
+            hsk::fused_lds_bytes((int)p->T, R, p->H, hsk::kModeDetect) > kLdsBudget) {
+            delete p;
+            return HS_ERR_UNSUPPORTED;
         }
-        if (R > hsk::kMaxTileRows || !fits(R)) { delete p; return HS_ERR_UNSUPPORTED; }
         p->tile_rows = R;
         p->row_blocks = (int)((p->T + R - 1) / R);
         p->lds_bytes = hsk::fused_lds_bytes((int)p->T, R, p->H, hsk::kModeDetect);

@@ -6,12 +6,14 @@
 
 namespace hsk {
 
-hipError_t launch_fused_f32(int mode, int H, const TileArgs& a, int64_t n, int g, int lds, hipStream_t s);
-hipError_t launch_fused_f16(int mode, int H, const TileArgs& a, int64_t n, int g, int lds, hipStream_t s);
-hipError_t launch_fused_bf16(int mode, int H, const TileArgs& a, int64_t n, int g, int lds, hipStream_t s);
-hipError_t launch_batched_f32(int H, const BatchArgs& b, int grid, int lds, hipStream_t s);
-hipError_t launch_batched_f16(int H, const BatchArgs& b, int grid, int lds, hipStream_t s);
-hipError_t launch_batched_bf16(int H, const BatchArgs& b, int grid, int lds, hipStream_t s);
+#define HS_DECL_GROUP(n, g)                                                                     \
+    hipError_t launch_fused_##n##_g##g(int mode, int H, const TileArgs& a, int64_t nt, int grid,  \
+                                       int lds, hipStream_t s);                                  \
+    hipError_t launch_batched_##n##_g##g(int H, const BatchArgs& b, int grid, int lds, hipStream_t s);
+#define HS_DECL_TYPE(n) HS_DECL_GROUP(n, 0) HS_DECL_GROUP(n, 1) HS_DECL_GROUP(n, 2) HS_DECL_GROUP(n, 3)
+HS_DECL_TYPE(f32)
+HS_DECL_TYPE(f16)
+HS_DECL_TYPE(bf16)
 
 __global__ void k_zero_i64(int64_t* p, int64_t n)
 {
@@ -20,46 +22,64 @@ __global__ void k_zero_i64(int64_t* p, int64_t n)
         p[e] = 0;
 }
 
-int fused_stage_words(int T, int R, int H)
-{
-    const int c = T / 2;
-    int worst = 0;
-    for (int r0 = 0; r0 < T; r0 += R) {
-        const int r1 = r0 + R < T ? r0 + R : T;
-        int tot = 0;
-        for (int m = 2; m <= H; ++m) {
-            const int nrow = (int)(floordiv(r1 - 1 - c, m) - floordiv(r0 - c, m) + 1);
-            tot += nrow * stage_pitch(m);
-        }
-        tot = (tot + 3) & ~3;      // the row table after it is read as float4
-        if (tot > worst) worst = tot;
-    }
-    return worst;
-}
-
 int fused_lds_bytes(int T, int R, int H, int mode)
 {
     (void)mode;
-    return 2 * fused_stage_words(T, R, H) * 4 + smem_tail_bytes(T, R, H);
+    return 2 * stage_words(H) * 4 + smem_tail_bytes(T, R, H);
 }
+
+#define HS_GROUP_CASES(call)                                                                    \
+    switch ((H - 1) / 4) {                                                                      \
+    case 0: return call(0);                                                                     \
+    case 1: return call(1);                                                                     \
+    case 2: return call(2);                                                                     \
+    case 3: return call(3);                                                                     \
+    }                                                                                           \
+    return hipErrorInvalidValue;
 
 hipError_t launch_fused(int mode, int dtype, int H, const TileArgs& a, int64_t n_tiles, int grid,
                         int lds_bytes, hipStream_t s)
 {
+    if (H < 1 || H > kMaxH) return hipErrorInvalidValue;
     switch (dtype) {
-    case HS_DTYPE_F32: return launch_fused_f32(mode, H, a, n_tiles, grid, lds_bytes, s);
-    case HS_DTYPE_F16: return launch_fused_f16(mode, H, a, n_tiles, grid, lds_bytes, s);
-    case HS_DTYPE_BF16: return launch_fused_bf16(mode, H, a, n_tiles, grid, lds_bytes, s);
+    case HS_DTYPE_F32: {
+#define HS_CALL(g) launch_fused_f32_g##g(mode, H, a, n_tiles, grid, lds_bytes, s)
+        HS_GROUP_CASES(HS_CALL)
+#undef HS_CALL
+    }
+    case HS_DTYPE_F16: {
+#define HS_CALL(g) launch_fused_f16_g##g(mode, H, a, n_tiles, grid, lds_bytes, s)
+        HS_GROUP_CASES(HS_CALL)
+#undef HS_CALL
+    }
+    case HS_DTYPE_BF16: {
+#define HS_CALL(g) launch_fused_bf16_g##g(mode, H, a, n_tiles, grid, lds_bytes, s)
+        HS_GROUP_CASES(HS_CALL)
+#undef HS_CALL
+    }
     }
     return hipErrorInvalidValue;
 }
 
 hipError_t launch_batched(int dtype, int H, const BatchArgs& b, int grid, int lds_bytes, hipStream_t s)
 {
+    if (H < 1 || H > kMaxH) return hipErrorInvalidValue;
     switch (dtype) {
-    case HS_DTYPE_F32: return launch_batched_f32(H, b, grid, lds_bytes, s);
-    case HS_DTYPE_F16: return launch_batched_f16(H, b, grid, lds_bytes, s);
-    case HS_DTYPE_BF16: return launch_batched_bf16(H, b, grid, lds_bytes, s);
+    case HS_DTYPE_F32: {
+#define HS_CALL(g) launch_batched_f32_g##g(H, b, grid, lds_bytes, s)
+        HS_GROUP_CASES(HS_CALL)
+#undef HS_CALL
+    }
+    case HS_DTYPE_F16: {
+#define HS_CALL(g) launch_batched_f16_g##g(H, b, grid, lds_bytes, s)
+        HS_GROUP_CASES(HS_CALL)
+#undef HS_CALL
+    }
+    case HS_DTYPE_BF16: {
+#define HS_CALL(g) launch_batched_bf16_g##g(H, b, grid, lds_bytes, s)
+        HS_GROUP_CASES(HS_CALL)
+#undef HS_CALL
+    }
     }
     return hipErrorInvalidValue;
 }

@@ -1,0 +1,5 @@
+// Fused kernels for bfloat16 FOP storage, H = 9..12.
+#define HS_INST_T bf16_t
+#define HS_INST_NAME bf16
+#define HS_INST_GROUP 2
+#include "hs_fused_inst.h"

@@ -1,0 +1,5 @@
+// Fused kernels for fp16 FOP storage, H = 5..8.
+#define HS_INST_T _Float16
+#define HS_INST_NAME f16
+#define HS_INST_GROUP 1
+#include "hs_fused_inst.h"

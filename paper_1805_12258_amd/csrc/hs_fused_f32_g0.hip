@@ -1,0 +1,5 @@
+// Fused kernels for fp32 FOP storage, H = 1..4.
+#define HS_INST_T float
+#define HS_INST_NAME f32
+#define HS_INST_GROUP 0
+#include "hs_fused_inst.h"

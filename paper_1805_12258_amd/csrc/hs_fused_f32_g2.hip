@@ -1,0 +1,5 @@
+// Fused kernels for fp32 FOP storage, H = 9..12.
+#define HS_INST_T float
+#define HS_INST_NAME f32
+#define HS_INST_GROUP 2
+#include "hs_fused_inst.h"

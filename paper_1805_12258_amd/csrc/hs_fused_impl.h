@@ -102,21 +102,35 @@ struct Smem {
     float* rowtab[2];             // per row: staged-row offsets of m = 2..H, then
                                   // the H thresholds (both entries alias when the
                                   // table covers the whole plane)
-    uint2* cand;                  // [kWaves][kWaveCandCap] per-wave candidate buffers
+    uint64_t* cand;               // [kWaves][kWaveCandCap] per-wave candidate buffers
+                                  // (bin word in the low half, power bits high)
     int* cnt;                     // [kMaxH] per-plane counts of the block
+    struct FlushParams* fp;       // where flushed candidates go
 };
 
-__device__ __forceinline__ Smem carve(float* lds, int stage_words, int T, int R, int H,
-                                      bool whole)
+// Candidate output of the FOP being processed, kept in LDS so that the
+// out-of-line flush needs only LDS pointers (few registers at the call).
+struct FlushParams {
+    hs_cand* out;
+    int64_t cap;
+    unsigned long long* total;   // counts[H]
+    int32_t s_bin;
+    uint32_t kmask;
+};
+static_assert(sizeof(FlushParams) <= kFlushParamBytes, "flush parameters");
+
+template <int H>
+__device__ __forceinline__ Smem carve(float* lds, int T, int R, bool whole)
 {
     Smem s;
     s.stage[0] = lds;
-    s.stage[1] = lds + stage_words;
-    s.rowtab[0] = lds + 2 * stage_words;
+    s.stage[1] = lds + stage_words(H);
+    s.rowtab[0] = lds + 2 * stage_words(H);
     const int trows = whole ? T : R;
     s.rowtab[1] = whole ? s.rowtab[0] : s.rowtab[0] + trows * row_table_stride(H);
-    s.cand = reinterpret_cast<uint2*>(s.rowtab[1] + trows * row_table_stride(H));
+    s.cand = reinterpret_cast<uint64_t*>(s.rowtab[1] + trows * row_table_stride(H));
     s.cnt = reinterpret_cast<int*>(s.cand + kWaves * kWaveCandCap);
+    s.fp = reinterpret_cast<FlushParams*>(s.cnt + kMaxH);
     return s;
 }
 
@@ -136,7 +150,7 @@ __device__ __forceinline__ uint64_t read_first_u64(uint64_t x)
 // Write a wave's buffered candidates to global memory (one atomic per wave)
 // and count them per plane in the block's LDS counters (the plane is read
 // back from each candidate word).
-__device__ __noinline__ void flush_wave(const uint2* wbuf, int n, hs_cand* out, int64_t cap,
+__device__ __forceinline__ void flush_wave(const uint64_t* wbuf, int n, hs_cand* out, int64_t cap,
                                            unsigned long long* total, int* block_cnt, int s_bin,
                                            uint32_t kmask)
 {
@@ -145,9 +159,9 @@ __device__ __noinline__ void flush_wave(const uint2* wbuf, int n, hs_cand* out, 
     if (lane == 0) base = atomicAdd(total, (unsigned long long)n);
     base = read_first_u64(base);
     for (int e = lane; e < n; e += 64) {
-        const uint2 c = wbuf[e];
-        atomicAdd(&block_cnt[(c.x >> s_bin) & kmask], 1);
-        if ((int64_t)(base + e) < cap) reinterpret_cast<uint2*>(out)[base + e] = c;
+        const uint64_t c = wbuf[e];
+        atomicAdd(&block_cnt[((uint32_t)c >> s_bin) & kmask], 1);
+        if ((int64_t)(base + e) < cap) reinterpret_cast<uint64_t*>(out)[base + e] = c;
     }
 }
 
@@ -165,12 +179,33 @@ __device__ __forceinline__ void flush_counts(const Smem& sh, unsigned long long*
     __syncthreads();
 }
 
+// Out-of-line flush of the calling wave's buffer (n entries): the rare path
+// inside the row loop, kept out of line so the loop stays small.
+__device__ __noinline__ void flush_call(int n, const uint64_t* wbuf, int* block_cnt,
+                                        const FlushParams* fp)
+{
+    flush_wave(wbuf, n, fp->out, fp->cap, fp->total, block_cnt, fp->s_bin, fp->kmask);
+}
+
+__device__ __forceinline__ void set_flush_params(const Smem& sh, hs_cand* out, int64_t cap,
+                                                 unsigned long long* total, int s_bin, uint32_t kmask)
+{
+    if (threadIdx.x == 0) {
+        sh.fp->out = out;
+        sh.fp->cap = cap;
+        sh.fp->total = total;
+        sh.fp->s_bin = s_bin;
+        sh.fp->kmask = kmask;
+    }
+}
+
 // Append the hits of one (row, plane) to the wave's LDS buffer.  Called by
 // the whole wave (uniform control flow): positions come from wave ballots.
+// A buffer without room for 64 more entries is flushed first.
 template <int V, int H>
 __device__ __forceinline__ void emit_hits(const float* acc, float t, int r, int k, int64_t jb,
                                           const TileArgs& a, const Smem& sh, WaveState<H>& ws,
-                                          uint2* wbuf)
+                                          uint64_t* wbuf)
 {
     const uint32_t hi = (uint32_t)(((uint64_t)r << a.s_row) | ((uint64_t)(k - 1) << a.s_bin));
 #pragma unroll
@@ -178,49 +213,122 @@ __device__ __forceinline__ void emit_hits(const float* acc, float t, int r, int 
         const bool hit = acc[v] > t;
         const uint64_t mk = __builtin_amdgcn_ballot_w64(hit);
         if (mk) {
-            if (hit) {
-                const int pos = ws.n + (int)__builtin_amdgcn_mbcnt_hi(
-                    (uint32_t)(mk >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mk, 0));
-                wbuf[pos] = make_uint2(hi | (uint32_t)(jb + v), __float_as_uint(acc[v]));
+            if (__builtin_expect(ws.n > kWaveCandCap - 64, 0)) {
+                flush_call(ws.n, wbuf, sh.cnt, sh.fp);
+                ws.n = 0;
             }
+            const int pre = (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(mk >> 32),
+                                                           __builtin_amdgcn_mbcnt_lo((uint32_t)mk, 0));
+            if (hit) wbuf[ws.n + pre] = ((uint64_t)__float_as_uint(acc[v]) << 32) | (hi | (uint32_t)(jb + v));
             ws.n += __builtin_popcountll(mk);
         }
     }
 }
 
-// Geometry of one row block (constant while a block walks the bin tiles of
-// that row block): source rows and staging layout of every stretch factor.
+// Flush the wave's buffer once it holds kFlushAt entries (between tiles).
+constexpr int kFlushAt = 64;
 template <int H>
-struct RowGeo {
-    int rb, r0, nr;
-    int a_lo[H + 1], nrow[H + 1], offm[H + 1];
-};
-
-template <int H>
-__device__ __forceinline__ void row_geo(const TileArgs& a, int rb, RowGeo<H>& g)
+__device__ __forceinline__ void maybe_flush(const Smem& sh, WaveState<H>& ws)
 {
-    g.rb = rb;
-    g.r0 = rb * a.R;
-    const int r1 = min(g.r0 + a.R, a.T);
-    g.nr = r1 - g.r0;
-    const int i_lo = g.r0 - a.c, i_hi = r1 - 1 - a.c;
-    int tot = 0;
-#pragma unroll
-    for (int m = 2; m <= H; ++m) {
-        g.a_lo[m] = floordiv32(i_lo, m);
-        g.nrow[m] = floordiv32(i_hi, m) - g.a_lo[m] + 1;
-        g.offm[m] = tot;
-        tot += g.nrow[m] * stage_pitch(m);
+    if (ws.n >= kFlushAt) {
+        flush_call(ws.n, sh.cand + (threadIdx.x >> 6) * kWaveCandCap, sh.cnt, sh.fp);
+        ws.n = 0;
     }
 }
 
+// Row block of a tile: rows [r0, r0 + nr) of the plane.
+struct RowGeo {
+    int rb, r0, nr;
+};
+
+__device__ __forceinline__ void row_geo(const TileArgs& a, int rb, RowGeo& g)
+{
+    g.rb = rb;
+    g.r0 = rb * a.R;
+    g.nr = min(g.r0 + a.R, a.T) - g.r0;
+}
+
+// First source row staged for stretch factor m in the row block starting at
+// plane row r0: floor((r0 - c) / m) + c (Eq. 1 with the template index i = r - c).
+template <int m>
+__device__ __forceinline__ int src_row_lo(int r0, int c)
+{
+    return floordiv32(r0 - c, m) + c;
+}
+
+// First source word staged for stretch factor m in the bin tile starting at j0.
+template <int m>
+__device__ __forceinline__ uint32_t src_col_lo(int j0)
+{
+    const uint32_t blo = (uint32_t)j0 / (uint32_t)m;
+    return stage_aligned(m) ? blo : (blo & ~3u);
+}
+
+// Per-lane byte offsets of this wave's LDS-DMA pieces, relative to the first
+// staged word of the piece's stretch factor (depend on the row pitch ld
+// only, so they are computed once per launch or FOP).  Lanes past the end of
+// a region get 0xffffffff, which every row limit rejects.
+template <int H>
+__device__ __forceinline__ void dma_offsets(int64_t ld, int elem_bytes, uint32_t (&voff)[stage_slot_regs(H)])
+{
+    const uint32_t lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const uint32_t ldb = (uint32_t)ld * (uint32_t)elem_bytes;
+#pragma unroll
+    for (int s = 0; s < stage_slots(H); ++s) {
+        const int g = s * kWaves + wave;
+        uint32_t off = 0xffffffffu;
+        static_for<2, H>([&](auto mc) {
+            constexpr int m = decltype(mc)::value;
+            constexpr int RW = stage_row_words(m);
+            if (g >= stage_chunk_begin(m) && g < stage_chunk_begin(m + 1)) {
+                const uint32_t w = ((uint32_t)(g - stage_chunk_begin(m)) * 64u + lane) * 4u;
+                if (w < (uint32_t)stage_region_words(m)) {
+                    const uint32_t row = w / RW, col = w - row * RW;
+                    off = row * ldb + col * (uint32_t)elem_bytes;
+                }
+            }
+        });
+        voff[s] = off;
+    }
+    if (stage_slots(H) == 0) voff[0] = 0xffffffffu;
+}
+
+// LDS-DMA of the pieces of wave W for the tile (r0, j0): piece g = s kWaves + W
+// of region m copies 64 x 16 bytes of source rows src_row_lo<m> + .. into the
+// staging buffer.  Source rows past the plane are masked (row limit); the
+// columns of a full bin tile all lie inside the plane's rows.
+template <int H, int W>
+__device__ __forceinline__ void dma_wave(const TileArgs& a, int r0, int j0, float* stage,
+                                         const uint32_t (&voff)[stage_slot_regs(H)])
+{
+    static_for<0, stage_slots(H) - 1>([&](auto sc) {   // empty for H = 1
+        constexpr int s = decltype(sc)::value;
+        constexpr int g = s * kWaves + W;
+        if constexpr (g < stage_total_chunks(H)) {
+            constexpr int m = stage_chunk_m(g);
+            constexpr int c = g - stage_chunk_begin(m);
+            const int lo = src_row_lo<m>(r0, a.c);
+            const char* base = reinterpret_cast<const char*>(a.fop) +
+                               ((int64_t)lo * a.ld + src_col_lo<m>(j0)) * 4;
+            const uint64_t lim64 = (uint64_t)(a.T - lo) * (uint64_t)a.ld * 4u;
+            const uint32_t lim = lim64 > 0xffffffffull ? 0xffffffffu : (uint32_t)lim64;
+            if (voff[s] < lim)
+                __builtin_amdgcn_global_load_lds(reinterpret_cast<const float*>(base + voff[s]),
+                                                 (lds_ptr_t)(stage + stage_offset(m) + c * kDmaWords),
+                                                 16, 0, 0);
+        }
+    });
+}
+
 // Start every load of tile (g.rb, bt): the shrunken source ranges into the
-// staging buffer `stage` (LDS-DMA for fp32), the m = 1 values of the wave's
-// rows into `x`, and (when the row table does not cover the whole plane) the
-// tile's row table into `rowtab`.  Nothing is waited for here.
-template <typename TIn, int H, int MODE>
-__device__ __forceinline__ void issue_tile(const TileArgs& a, const RowGeo<H>& g, int bt,
+// staging buffer `stage`, the m = 1 values of the wave's rows into `x`, and
+// (when the row table does not cover the whole plane) the tile's row table
+// into `rowtab`.  Nothing is waited for here.
+template <typename TIn, int H, int MODE, bool FULL>
+__device__ __forceinline__ void issue_tile(const TileArgs& a, const RowGeo& g, int bt,
                                            float* stage, float* rowtab,
+                                           const uint32_t (&voff)[stage_slot_regs(H)],
                                            float (&x)[kRowsPerWave][kV])
 {
     using Ld = Io<TIn>;
@@ -229,54 +337,55 @@ __device__ __forceinline__ void issue_tile(const TileArgs& a, const RowGeo<H>& g
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int N = (int)a.N;
-    // Bin arithmetic is 32-bit (N < 2^31): scalar 64-bit division would cost
-    // more than the tile's whole row loop.
+    // Bin arithmetic is 32-bit (N < 2^31).
     const int j0 = bt * kTileBins;
-    // In a full tile every staged word up to the pitch lies inside the plane
-    // (floor(j0/m) + pitch(m) <= N for m >= 2), so only the last chunk of a
-    // region needs a mask; the partial last tile checks each column.
-    const bool full = j0 + kTileBins <= N;
     const int64_t ld = a.ld;
-    const uint32_t ld32 = (uint32_t)ld;
 
-    // 1. Source ranges.  Region m holds nrow[m] rows of stage_pitch(m) words
-    // back to back; every wave instruction fills 64 consecutive words, each
-    // lane computing its own source offset.
-#pragma unroll
-    for (int m = 2; m <= H; ++m) {
-        const int P = stage_pitch(m);
-        const int words = g.nrow[m] * P;
-        const int nchunk = (words + 63) >> 6;
-        const int blo = (int)((uint32_t)j0 / (uint32_t)m);
-        const int span = full ? P : (int)((uint32_t)(min(j0 + kTileBins, N) - 1) / (uint32_t)m) - blo + 1;
-        const T* base = fop + (int64_t)(g.a_lo[m] + a.c) * ld + blo;   // first source word
-        for (int ch = wave; ch < nchunk; ch += kWaves) {
-            const uint32_t e = ((uint32_t)ch << 6) + lane;
-            const uint32_t row = e / (uint32_t)P;
-            const uint32_t col = e - row * (uint32_t)P;
-            if (e < (uint32_t)words && (full || col < (uint32_t)span)) {
-                const T* src = base + (row * ld32 + col);
-                if constexpr (sizeof(T) == 4) {
-                    __builtin_amdgcn_global_load_lds(src, (lds_ptr_t)(stage + g.offm[m] + (ch << 6)), 4, 0, 0);
-                } else {
-                    stage[g.offm[m] + e] = Ld::one(src) * a.inv_scale;
-                }
-            }
+    // 1. Source ranges.  fp32 full tiles (j0 + kTileBins <= N): LDS-DMA
+    // pieces with precomputed lane offsets.  Otherwise every thread converts
+    // words one at a time (reduced precision is scaled).
+    if constexpr (sizeof(T) == 4 && FULL) {
+        switch (wave) {
+        case 0: dma_wave<H, 0>(a, g.r0, j0, stage, voff); break;
+        case 1: dma_wave<H, 1>(a, g.r0, j0, stage, voff); break;
+        case 2: dma_wave<H, 2>(a, g.r0, j0, stage, voff); break;
+        case 3: dma_wave<H, 3>(a, g.r0, j0, stage, voff); break;
+        case 4: dma_wave<H, 4>(a, g.r0, j0, stage, voff); break;
+        case 5: dma_wave<H, 5>(a, g.r0, j0, stage, voff); break;
+        case 6: dma_wave<H, 6>(a, g.r0, j0, stage, voff); break;
+        default: dma_wave<H, 7>(a, g.r0, j0, stage, voff); break;
         }
+    } else {
+        static_for<2, H>([&](auto mc) {
+            constexpr int m = decltype(mc)::value;
+            constexpr int RW = stage_row_words(m);
+            const int lo = src_row_lo<m>(g.r0, a.c);
+            const int cb = (int)src_col_lo<m>(j0);
+            for (int e = threadIdx.x; e < stage_region_words(m); e += kThreads) {
+                const int row = e / RW, col = e - row * RW;
+                float v = 0.0f;
+                if (lo + row < a.T && (FULL || cb + col < N)) {
+                    v = Ld::one(fop + (int64_t)(lo + row) * ld + cb + col);
+                    if (Scaled<TIn>::value) v *= a.inv_scale;
+                }
+                stage[stage_offset(m) + e] = v;
+            }
+        });
     }
 
     // 2. The m = 1 values of every row this wave owns.
-    const int jb = j0 + kV * lane;
-    if (full) {
+    if constexpr (FULL) {
         // unconditional loads (rows past the tile re-read its last row and
         // are ignored) land straight in their registers, so nothing waits
         // for them before the tile is summed
 #pragma unroll
         for (int q = 0; q < kRowsPerWave; ++q) {
             const int rr = min(wave + kWaves * q, g.nr - 1);
-            Ld::four(fop + (int64_t)(g.r0 + rr) * ld + jb, x[q]);
+            const T* rowp = fop + (int64_t)(g.r0 + rr) * ld + j0;
+            Ld::four(rowp + kV * lane, x[q]);
         }
     } else {
+        const int jb = j0 + kV * lane;
 #pragma unroll
         for (int q = 0; q < kRowsPerWave; ++q) {
             const int rr = wave + kWaves * q;
@@ -297,17 +406,20 @@ __device__ __forceinline__ void issue_tile(const TileArgs& a, const RowGeo<H>& g
         constexpr int SO = row_table_thr_offset(H);
         for (int e = threadIdx.x; e < g.nr * RS; e += kThreads) {
             const int rr = e / RS, col = e - rr * RS;
-            const int i = g.r0 + rr - a.c;
+            const int r = g.r0 + rr;
             float val = 0.0f;
             if (col < H - 1) {
                 int off = 0;
-#pragma unroll
-                for (int m = 2; m <= H; ++m)
-                    if (col == m - 2) off = g.offm[m] + (floordiv32(i, m) - g.a_lo[m]) * stage_pitch(m);
+                static_for<2, H>([&](auto mc) {
+                    constexpr int m = decltype(mc)::value;
+                    if (col == m - 2)
+                        off = stage_offset(m) +
+                              (src_row_lo<m>(r, a.c) - src_row_lo<m>(g.r0, a.c)) * stage_row_words(m);
+                });
                 val = __int_as_float(off);
             } else if (MODE == kModeDetect && col >= SO && col < SO + H) {
                 // thresholds exist only in the detection mode (a.ta is null otherwise)
-                val = a.ta[(int64_t)(col - SO) * a.T + g.r0 + rr];
+                val = a.ta[(int64_t)(col - SO) * a.T + r];
             }
             rowtab[e] = val;
         }
@@ -316,8 +428,8 @@ __device__ __forceinline__ void issue_tile(const TileArgs& a, const RowGeo<H>& g
 
 // Form the planes of one tile whose loads have completed (after a barrier):
 // HP_k for k = 1..H in the order of Eq. 2, detected or stored.
-template <typename TIn, int H, int MODE>
-__device__ __forceinline__ void compute_tile(const TileArgs& a, const RowGeo<H>& g, int bt,
+template <typename TIn, int H, int MODE, bool FULL>
+__device__ __forceinline__ void compute_tile(const TileArgs& a, const RowGeo& g, int bt,
                                              const Smem& sh, const float* stage,
                                              const float* rowtab,
                                              const float (&x)[kRowsPerWave][kV], WaveState<H>& ws)
@@ -329,23 +441,23 @@ __device__ __forceinline__ void compute_tile(const TileArgs& a, const RowGeo<H>&
     const int nr = g.nr;
     const int N = (int)a.N;
     const int jb = j0 + kV * lane;
-    const bool tile_full = j0 + kTileBins <= N;        // wave-uniform
     constexpr int RS = row_table_stride(H);
     constexpr int SO = row_table_thr_offset(H);
     const int trow0 = a.table_whole ? r0 : 0;          // table row of tile row 0
 
     // Per-lane view of the staged rows: the lane's first source word of each
-    // stretch factor and where its kV bins cross to the next word.
+    // stretch factor (relative to the staged row, which starts at
+    // src_col_lo) and where its kV bins cross to the next word.
     int loff[H + 1], sig[H + 1];
 #pragma unroll
     for (int m = 2; m <= H; ++m) {
         const int blo = (int)((uint32_t)j0 / (uint32_t)m);
         const int t = (j0 - blo * m) + kV * lane;     // (j0 mod m) + kV * lane
-        loff[m] = t / m;
+        loff[m] = t / m + (stage_aligned(m) ? 0 : (blo & 3));
         sig[m] = t % m;
     }
 
-    uint2* wbuf = sh.cand + wave * kWaveCandCap;
+    uint64_t* wbuf = sh.cand + wave * kWaveCandCap;
     // rows unrolled with static register indices (a dynamic index into the
     // prefetched rows would make every load complete before the tile starts)
 #pragma unroll
@@ -357,12 +469,12 @@ __device__ __forceinline__ void compute_tile(const TileArgs& a, const RowGeo<H>&
         // so their latencies overlap; the candidate writes below could
         // otherwise alias them and serialise every read.
         const float* rt = rowtab + (trow0 + rr) * RS;
+        // plain float reads (merged into 16-byte reads): LDS accesses through
+        // aggregate types carry no type-based alias information, and the
+        // compiler then orders them after every LDS-DMA in flight
         float tab[RS];
 #pragma unroll
-        for (int u = 0; u < RS / 4; ++u) {
-            const float4 q4 = reinterpret_cast<const float4*>(rt)[u];
-            tab[4 * u] = q4.x; tab[4 * u + 1] = q4.y; tab[4 * u + 2] = q4.z; tab[4 * u + 3] = q4.w;
-        }
+        for (int u = 0; u < RS; ++u) tab[u] = rt[u];
         float w[H + 1][2];
         static_for<2, H>([&](auto mc) {
             constexpr int m = decltype(mc)::value;
@@ -388,17 +500,11 @@ __device__ __forceinline__ void compute_tile(const TileArgs& a, const RowGeo<H>&
                 // cheap wave test first: the largest of the lane's kV sums
                 // (NaN operands are ignored by max and fail the compare)
                 const float mx = fmaxf(fmaxf(acc[0], acc[1]), fmaxf(acc[2], acc[3]));
-                if (__builtin_expect(__builtin_amdgcn_ballot_w64(mx > t) != 0, 0)) {
-                    // room for every hit of this (row, plane): at most kV per lane
-                    if (ws.n > kWaveCandCap - kV * 64) {
-                        flush_wave(wbuf, ws.n, a.out, a.cap, &a.counts[H], sh.cnt, a.s_bin, a.kmask);
-                        ws.n = 0;
-                    }
+                if (__builtin_expect(__builtin_amdgcn_ballot_w64(mx > t) != 0, 0))
                     emit_hits<kV, H>(acc, t, r, k, jb, a, sh, ws, wbuf);
-                }
             } else {
                 float* dst = a.hp + ((int64_t)(k - 1) * a.T + r) * N + jb;
-                if (tile_full && (N & 3) == 0) {
+                if (FULL && (N & 3) == 0) {
                     *reinterpret_cast<float4*>(dst) = make_float4(acc[0], acc[1], acc[2], acc[3]);
                 } else {
 #pragma unroll
@@ -434,42 +540,62 @@ __device__ __forceinline__ void compute_tile(const TileArgs& a, const RowGeo<H>&
     }
 }
 
-// Tiles [begin, end) of a contiguous run in row-block-major order (tile
-// t = rb * n_bt + bt), processed with the loads of tile t+1 in flight while
-// tile t is summed.  The two halves of the loop body use the two buffers with
-// static register indices, so no wait on the in-flight loads is implied.
+// Tiles [begin, end) of a contiguous run.  Tiles are numbered with the full
+// bin tiles first, row-block-major (t = rb * n_full + bt), then the partial
+// last bin tile of every row block (when N is not a multiple of kTileBins).
+// Full tiles are processed with the loads of tile t+1 in flight while tile t
+// is summed; the two halves of the loop body use the two buffers with static
+// register indices, so no wait on the in-flight loads is implied.  Partial
+// tiles take a plain load-wait-compute loop with bounds checks.
 template <typename TIn, int H, int MODE>
-__device__ __forceinline__ void run_tiles(const TileArgs& a, int64_t begin, int64_t end, int n_bt,
-                                          const Smem& sh, WaveState<H>& ws)
+__device__ __forceinline__ void run_tiles(const TileArgs& a, int64_t begin, int64_t end,
+                                          const Smem& sh, const uint32_t (&voff)[stage_slot_regs(H)],
+                                          WaveState<H>& ws)
 {
-    if (begin >= end) return;
+    const int n_full = (int)(a.N / kTileBins);
+    const int64_t full_total = (int64_t)a.row_blocks * n_full;
     float xa[kRowsPerWave][kV], xb[kRowsPerWave][kV];
-    int rb = (int)(begin / n_bt);
-    int bt = (int)(begin - (int64_t)rb * n_bt);
-    RowGeo<H> gc, gn;                 // row geometry of the current / next tile
-    row_geo<H>(a, rb, gc);
-    gn = gc;
-    __syncthreads();   // the previous run is done with both buffers
-    issue_tile<TIn, H, MODE>(a, gc, bt, sh.stage[0], sh.rowtab[0], xa);
-    int64_t t = begin;
-    for (;;) {
-        int bt1 = bt + 1;
-        if (bt1 == n_bt) { bt1 = 0; row_geo<H>(a, gc.rb + 1, gn); }
-        __builtin_amdgcn_s_waitcnt(0);
-        __syncthreads();
-        if (t + 1 < end) issue_tile<TIn, H, MODE>(a, gn, bt1, sh.stage[1], sh.rowtab[1], xb);
-        compute_tile<TIn, H, MODE>(a, gc, bt, sh, sh.stage[0], sh.rowtab[0], xa, ws);
-        gc = gn; bt = bt1;
-        if (++t >= end) break;
+    const int64_t fend = end < full_total ? end : full_total;
+    if (begin < fend) {
+        int rb = (int)(begin / n_full);
+        int bt = (int)(begin - (int64_t)rb * n_full);
+        RowGeo gc, gn;                    // row geometry of the current / next tile
+        row_geo(a, rb, gc);
+        gn = gc;
+        __syncthreads();   // the previous run is done with both buffers
+        issue_tile<TIn, H, MODE, true>(a, gc, bt, sh.stage[0], sh.rowtab[0], voff, xa);
+        int64_t t = begin;
+        for (;;) {
+            int bt1 = bt + 1;
+            if (bt1 == n_full) { bt1 = 0; row_geo(a, gc.rb + 1, gn); }
+            __builtin_amdgcn_s_waitcnt(0);
+            __syncthreads();
+            if (t + 1 < fend) issue_tile<TIn, H, MODE, true>(a, gn, bt1, sh.stage[1], sh.rowtab[1], voff, xb);
+            compute_tile<TIn, H, MODE, true>(a, gc, bt, sh, sh.stage[0], sh.rowtab[0], xa, ws);
+            if (MODE == kModeDetect) maybe_flush<H>(sh, ws);
+            gc = gn; bt = bt1;
+            if (++t >= fend) break;
 
-        bt1 = bt + 1;
-        if (bt1 == n_bt) { bt1 = 0; row_geo<H>(a, gc.rb + 1, gn); }
+            bt1 = bt + 1;
+            if (bt1 == n_full) { bt1 = 0; row_geo(a, gc.rb + 1, gn); }
+            __builtin_amdgcn_s_waitcnt(0);
+            __syncthreads();
+            if (t + 1 < fend) issue_tile<TIn, H, MODE, true>(a, gn, bt1, sh.stage[0], sh.rowtab[0], voff, xa);
+            compute_tile<TIn, H, MODE, true>(a, gc, bt, sh, sh.stage[1], sh.rowtab[1], xb, ws);
+            if (MODE == kModeDetect) maybe_flush<H>(sh, ws);
+            gc = gn; bt = bt1;
+            if (++t >= fend) break;
+        }
+    }
+    for (int64_t t = begin > full_total ? begin : full_total; t < end; ++t) {
+        RowGeo g;
+        row_geo(a, (int)(t - full_total), g);
+        __syncthreads();   // the buffers are free
+        issue_tile<TIn, H, MODE, false>(a, g, n_full, sh.stage[0], sh.rowtab[0], voff, xa);
         __builtin_amdgcn_s_waitcnt(0);
         __syncthreads();
-        if (t + 1 < end) issue_tile<TIn, H, MODE>(a, gn, bt1, sh.stage[0], sh.rowtab[0], xa);
-        compute_tile<TIn, H, MODE>(a, gc, bt, sh, sh.stage[1], sh.rowtab[1], xb, ws);
-        gc = gn; bt = bt1;
-        if (++t >= end) break;
+        compute_tile<TIn, H, MODE, false>(a, g, n_full, sh, sh.stage[0], sh.rowtab[0], xa, ws);
+        if (MODE == kModeDetect) maybe_flush<H>(sh, ws);
     }
 }
 
@@ -485,17 +611,14 @@ __device__ __forceinline__ void build_whole_table(int T, int R, int c, const flo
         const int r = e / RS, col = e - r * RS;
         float val = 0.0f;
         if (col < H - 1) {
-            const int rb = r / R;
-            const int r0 = rb * R, r1 = min(r0 + R, T);
-            const int i_lo = r0 - c, i_hi = r1 - 1 - c, i = r - c;
-            int off = 0, sel = 0;
-#pragma unroll
-            for (int m = 2; m <= H; ++m) {
-                const int alo = floordiv32(i_lo, m);
-                if (col == m - 2) sel = off + (floordiv32(i, m) - alo) * stage_pitch(m);
-                off += (floordiv32(i_hi, m) - alo + 1) * stage_pitch(m);
-            }
-            val = __int_as_float(sel);
+            const int r0 = (r / R) * R;
+            int off = 0;
+            static_for<2, H>([&](auto mc) {
+                constexpr int m = decltype(mc)::value;
+                if (col == m - 2)
+                    off = stage_offset(m) + (src_row_lo<m>(r, c) - src_row_lo<m>(r0, c)) * stage_row_words(m);
+            });
+            val = __int_as_float(off);
         } else if (MODE == kModeDetect && col >= SO && col < SO + H) {
             val = ta[(int64_t)(col - SO) * T + r];
         }
@@ -515,19 +638,23 @@ __device__ __forceinline__ void block_chunk(int64_t n, int64_t& t_begin, int64_t
 template <int H> constexpr int fused_min_waves() { return 1; }
 
 template <typename TIn, int H, int MODE>
-__global__ __launch_bounds__(kThreads, fused_min_waves<H>()) void k_fused(TileArgs a, int stage_words,
-                                                                          int64_t n_tiles)
+__global__ __launch_bounds__(kThreads, fused_min_waves<H>()) void k_fused(TileArgs a, int64_t n_tiles)
 {
     extern __shared__ __align__(16) float lds[];
-    const Smem sh = carve(lds, stage_words, a.T, a.R, H, a.table_whole != 0);
+    const Smem sh = carve<H>(lds, a.T, a.R, a.table_whole != 0);
     WaveState<H> ws;
     ws.n = 0;
     if (threadIdx.x < kMaxH) sh.cnt[threadIdx.x] = 0;
     if (a.table_whole) build_whole_table<H, MODE>(a.T, a.R, a.c, a.ta, sh.rowtab[0]);
 
+    uint32_t voff[stage_slot_regs(H)];
+    dma_offsets<H>(a.ld, 4, voff);
+
+    if (MODE == kModeDetect) set_flush_params(sh, a.out, a.cap, &a.counts[H], a.s_bin, a.kmask);
+
     int64_t t0, t1;
     block_chunk(n_tiles, t0, t1);
-    run_tiles<TIn, H, MODE>(a, t0, t1, (int)((a.N + kTileBins - 1) / kTileBins), sh, ws);
+    run_tiles<TIn, H, MODE>(a, t0, t1, sh, voff, ws);
 
     if constexpr (MODE == kModeDetect) {
         if (ws.n) flush_wave(sh.cand + (threadIdx.x >> 6) * kWaveCandCap, ws.n, a.out, a.cap,
@@ -538,10 +665,10 @@ __global__ __launch_bounds__(kThreads, fused_min_waves<H>()) void k_fused(TileAr
 
 // Batched persistent kernel: the grid walks the tiles of every FOP.
 template <typename TIn, int H>
-__global__ __launch_bounds__(kThreads, fused_min_waves<H>()) void k_batched(BatchArgs b, int stage_words)
+__global__ __launch_bounds__(kThreads, fused_min_waves<H>()) void k_batched(BatchArgs b)
 {
     extern __shared__ __align__(16) float lds[];
-    const Smem sh = carve(lds, stage_words, b.T, b.R, H, b.table_whole != 0);
+    const Smem sh = carve<H>(lds, b.T, b.R, b.table_whole != 0);
     WaveState<H> ws;
     ws.n = 0;
     if (threadIdx.x < kMaxH) sh.cnt[threadIdx.x] = 0;
@@ -582,14 +709,18 @@ __global__ __launch_bounds__(kThreads, fused_min_waves<H>()) void k_batched(Batc
         a.kmask = b.kmask;
         a.table_whole = b.table_whole;
         a.hp = nullptr;
+        constexpr int eb = sizeof(typename Io<TIn>::T);
         const bool ok = ((reinterpret_cast<uintptr_t>(a.fop) & 15) == 0) &&
-                        (a.ld % align_elems == 0) && a.ld >= a.N;
+                        (a.ld % align_elems == 0) && a.ld >= a.N &&
+                        (a.ld * stage_rows(2) + kTileBins) * eb < ((int64_t)1 << 32);
         if (!ok) {
             if (threadIdx.x == 0 && tf == fb) a.counts[H] = ~0ull;
         } else {
+            uint32_t voff[stage_slot_regs(H)];
+            dma_offsets<H>(a.ld, 4, voff);
+            set_flush_params(sh, a.out, a.cap, &a.counts[H], a.s_bin, a.kmask);
             // tiles of this FOP segment, numbered from the FOP's first tile
-            run_tiles<TIn, H, kModeDetect>(a, tf - fb, fe - fb, (int)((a.N + kTileBins - 1) / kTileBins),
-                                           sh, ws);
+            run_tiles<TIn, H, kModeDetect>(a, tf - fb, fe - fb, sh, voff, ws);
             if (ws.n) {
                 flush_wave(sh.cand + (threadIdx.x >> 6) * kWaveCandCap, ws.n, a.out, a.cap,
                            &a.counts[H], sh.cnt, a.s_bin, a.kmask);
@@ -625,17 +756,16 @@ template <typename TIn, int H>
 static hipError_t launch_fused_t(int mode, const TileArgs& a, int64_t n_tiles, int grid,
                                  int lds_bytes, hipStream_t s)
 {
-    const int stage_words = (lds_bytes - smem_tail_bytes(a.T, a.R, H)) / 8;
     if (mode == kModeDetect) {
         auto k = k_fused<TIn, H, kModeDetect>;
         (void)hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, lds_bytes);
         const int g = resident_grid(k, lds_bytes, n_tiles, grid);
-        hipLaunchKernelGGL(k, dim3(g), dim3(kThreads), lds_bytes, s, a, stage_words, n_tiles);
+        hipLaunchKernelGGL(k, dim3(g), dim3(kThreads), lds_bytes, s, a, n_tiles);
     } else {
         auto k = k_fused<TIn, H, kModeSum>;
         (void)hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, lds_bytes);
         const int g = resident_grid(k, lds_bytes, n_tiles, grid);
-        hipLaunchKernelGGL(k, dim3(g), dim3(kThreads), lds_bytes, s, a, stage_words, n_tiles);
+        hipLaunchKernelGGL(k, dim3(g), dim3(kThreads), lds_bytes, s, a, n_tiles);
     }
     return hipGetLastError();
 }
@@ -643,25 +773,11 @@ static hipError_t launch_fused_t(int mode, const TileArgs& a, int64_t n_tiles, i
 template <typename TIn, int H>
 static hipError_t launch_batched_t(const BatchArgs& b, int grid, int lds_bytes, hipStream_t s)
 {
-    const int stage_words = (lds_bytes - smem_tail_bytes(b.T, b.R, H)) / 8;
     auto k = k_batched<TIn, H>;
     (void)hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, lds_bytes);
     const int g = resident_grid(k, lds_bytes, b.tiles_total, grid);
-    hipLaunchKernelGGL(k, dim3(g), dim3(kThreads), lds_bytes, s, b, stage_words);
+    hipLaunchKernelGGL(k, dim3(g), dim3(kThreads), lds_bytes, s, b);
     return hipGetLastError();
 }
-
-#define HS_H_CASES(F, ...)                                                                        \
-    switch (H) {                                                                                  \
-    case 1: return F<1>(__VA_ARGS__);   case 2: return F<2>(__VA_ARGS__);                         \
-    case 3: return F<3>(__VA_ARGS__);   case 4: return F<4>(__VA_ARGS__);                         \
-    case 5: return F<5>(__VA_ARGS__);   case 6: return F<6>(__VA_ARGS__);                         \
-    case 7: return F<7>(__VA_ARGS__);   case 8: return F<8>(__VA_ARGS__);                         \
-    case 9: return F<9>(__VA_ARGS__);   case 10: return F<10>(__VA_ARGS__);                       \
-    case 11: return F<11>(__VA_ARGS__); case 12: return F<12>(__VA_ARGS__);                       \
-    case 13: return F<13>(__VA_ARGS__); case 14: return F<14>(__VA_ARGS__);                       \
-    case 15: return F<15>(__VA_ARGS__); case 16: return F<16>(__VA_ARGS__);                       \
-    default: return hipErrorInvalidValue;                                                         \
-    }
 
 }  // namespace hsk

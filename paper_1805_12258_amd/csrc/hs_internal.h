@@ -14,27 +14,78 @@ namespace hsk {
 // Tile geometry of the fused kernels.  A tile is a block of at most
 // kMaxTileRows template rows times kTileBins consecutive bins; each lane owns
 // kV consecutive bins of one row at a time, and wave w of a block handles the
-// tile rows w, w + kWaves, w + 2 kWaves.
+// tile rows w + q kWaves, q < kRowsPerWave.
 constexpr int kLanes = 64;
 constexpr int kV = 4;
 constexpr int kTileBins = kV * kLanes;   // 256
 constexpr int kWaves = 8;
 constexpr int kThreads = kWaves * kLanes;
 constexpr int kRowsPerWave = 4;
-constexpr int kMaxTileRows = kWaves * kRowsPerWave;   // 48
+constexpr int kMaxTileRows = kWaves * kRowsPerWave;   // 32
 constexpr int kWaveCandCap = 320;        // per-wave LDS candidate buffer (>= kV*64 + 64)
 constexpr int kMaxH = 16;
+constexpr int kFlushParamBytes = 32;     // candidate-output parameters kept in LDS
 
-// Words reserved per staged source row of stretch factor m: the largest
-// number of distinct floor(j/m) over kTileBins consecutive bins starting at a
+// Source words a tile needs per row of stretch factor m: the largest number
+// of distinct floor(j/m) over kTileBins consecutive bins starting at a
 // multiple of kTileBins (j0 mod m is then a multiple of gcd(kTileBins, m),
-// which for a power-of-two tile width is the lowest set bit of m).  The rows
-// of one stretch factor are stored back to back with this pitch.
+// which for a power-of-two tile width is the lowest set bit of m).
 static_assert((kTileBins & (kTileBins - 1)) == 0, "tile width must be a power of two");
 __host__ __device__ constexpr int stage_pitch(int m)
 {
     return (m - (m & -m) + kTileBins - 1) / m + 1;
 }
+
+// Staging layout in LDS, fixed at compile time for tiles of up to
+// kMaxTileRows rows.  Region m (m = 2..H) holds stage_rows(m) source rows of
+// stage_row_words(m) words.  Rows are loaded in 16-byte pieces (LDS-DMA of
+// four words per lane), so a row starts at the source word floor(j0/m)
+// rounded down to a multiple of four; when m divides kTileBins / 4 that word
+// is already aligned.
+__host__ __device__ constexpr bool stage_aligned(int m) { return (kTileBins / 4) % m == 0; }
+__host__ __device__ constexpr int stage_row_words(int m)
+{
+    return (stage_pitch(m) + (stage_aligned(m) ? 0 : 3) + 3) & ~3;
+}
+// Most distinct floor(i/m) over kMaxTileRows consecutive template indices.
+__host__ __device__ constexpr int stage_rows(int m) { return (kMaxTileRows + m - 2) / m + 1; }
+__host__ __device__ constexpr int stage_region_words(int m) { return stage_rows(m) * stage_row_words(m); }
+__host__ __device__ constexpr int stage_offset(int m)
+{
+    int o = 0;
+    for (int k = 2; k < m; ++k) o += stage_region_words(k);
+    return o;
+}
+// Words of one staging buffer for H planes.
+__host__ __device__ constexpr int stage_words(int H) { return stage_offset(H + 1); }
+
+// LDS-DMA pieces: one wave instruction moves 64 lanes x 4 words.  Region m is
+// covered by stage_chunks(m) pieces (the last one partly masked); pieces are
+// numbered across regions and piece g is issued by wave g % kWaves.
+constexpr int kDmaWords = kLanes * 4;
+__host__ __device__ constexpr int stage_chunks(int m)
+{
+    return (stage_region_words(m) + kDmaWords - 1) / kDmaWords;
+}
+__host__ __device__ constexpr int stage_chunk_begin(int m)
+{
+    int o = 0;
+    for (int k = 2; k < m; ++k) o += stage_chunks(k);
+    return o;
+}
+__host__ __device__ constexpr int stage_total_chunks(int H) { return stage_chunk_begin(H + 1); }
+__host__ __device__ constexpr int stage_chunk_m(int g)
+{
+    int m = 2;
+    while (g >= stage_chunk_begin(m + 1)) ++m;
+    return m;
+}
+__host__ __device__ constexpr int stage_slots(int H)
+{
+    return (stage_total_chunks(H) + kWaves - 1) / kWaves;
+}
+// Registers holding a wave's piece offsets (at least one, for H = 1).
+__host__ __device__ constexpr int stage_slot_regs(int H) { return stage_slots(H) > 0 ? stage_slots(H) : 1; }
 
 // Row table of a tile: per tile row, the staging offsets of stretch factors
 // 2..H (padded to 4 words) followed by the H thresholds (padded to 4).
@@ -53,12 +104,12 @@ __host__ __device__ constexpr bool table_whole(int T, int H)
 }
 
 // LDS bytes after the two staging buffers: the row table (two per-tile
-// copies unless it covers the whole plane), the per-wave candidate buffers
-// and the per-plane counters of the block.
+// copies unless it covers the whole plane), the per-wave candidate buffers,
+// the per-plane counters of the block and the candidate-output parameters.
 __host__ __device__ constexpr int smem_tail_bytes(int T, int R, int H)
 {
     return (table_whole(T, H) ? T : 2 * R) * row_table_stride(H) * 4 +
-           kWaves * kWaveCandCap * 8 + kMaxH * 4;
+           kWaves * kWaveCandCap * 8 + kMaxH * 4 + kFlushParamBytes;
 }
 
 __host__ __device__ inline int64_t floordiv(int64_t a, int64_t b)
@@ -118,11 +169,8 @@ struct BatchArgs {
 
 enum Mode { kModeDetect = 0, kModeSum = 1 };
 
-// LDS bytes of the fused kernel for a tile of `rows` rows starting at every
-// admissible row offset (maximum over the row blocks of the plan).
+// LDS bytes of the fused kernel for a plan (two staging buffers + tail).
 int fused_lds_bytes(int T, int R, int H, int mode);
-// Words of the staged source region alone (largest over the row blocks).
-int fused_stage_words(int T, int R, int H);
 
 hipError_t launch_fused(int mode, int dtype, int H, const TileArgs& a, int64_t n_tiles,
                         int grid, int lds_bytes, hipStream_t s);
