@@ -33,7 +33,8 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 KERNEL_SOURCES = ["paper_1805_12258_amd/csrc/hs_fused_impl.h",
-                  "paper_1805_12258_amd/csrc/hs_fused_f32.hip",
+                  "paper_1805_12258_amd/csrc/hs_fused_inst.h",
+                  "paper_1805_12258_amd/csrc/hs_fused_f32_g1.hip",
                   "paper_1805_12258_amd/csrc/hs_internal.h"]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "ska_detect_f32_traffic.json")
 
