@@ -147,31 +147,39 @@ hs_status hs_detect_batched(const hs_plan* plan, const void* const* fops, const 
                             const int64_t* caps, int64_t* counts, void* stream);
 
 /* Sort n candidates in place into the canonical order: ascending CL1 word
- * (row, then plane, then bin; CL1 words are unique within one FOP).
- * `work` is device scratch of at least hs_sort_workspace_bytes(n) bytes. */
+ * (row, then plane, then bin; CL1 words are unique within one FOP), a stable
+ * radix sort on the low 32 bits of each 8-byte entry.  `work` is device
+ * scratch of at least hs_sort_workspace_bytes(n) bytes (that query needs the
+ * current HIP device; it returns 0 for n <= 1 or when no device answers). */
 size_t hs_sort_workspace_bytes(int64_t n);
 hs_status hs_sort_candidates(hs_cand* cand, int64_t n, void* work, void* stream);
 
 /* Vector-Jacobian product of hs_sum (the transpose of Eq. 1-2): given
- * g = dL/dHP [n_hp][N_temp][N_chan] fp32, overwrites dfop [N_temp][N_chan]
- * fp32 with dL/dFOP in unscaled units.  `work` is device scratch of
- * hs_backward_workspace_bytes(plan) bytes.  Deterministic: the same input
- * gives bitwise the same output. */
+ * g = dL/dHP [n_hp][N_temp][N_chan] fp32 (leading dimension N_chan),
+ * overwrites dfop [N_temp][N_chan] fp32 with
+ *   dL/dFOP(a, b) = sum_{m=1..n_hp} sum over the m x m box of points (r, j)
+ *                   with floor((r - c)/m) + c = a and floor(j/m) = b of
+ *                   G_m(r, j),   G_m = sum_{k >= m} g_k,  c = N_temp / 2,
+ * in unscaled units.  `work` is device scratch of
+ * hs_backward_workspace_bytes(plan) bytes (per-tile partial sums).
+ * Deterministic: no floating-point atomics, so the same input gives bitwise
+ * the same output.  Single-FOP plans only. */
 size_t hs_backward_workspace_bytes(const hs_plan* plan);
 hs_status hs_sum_backward(const hs_plan* plan, const float* g, float* dfop, void* work,
                           void* stream);
 
-/* Log-sum-exp statistic of each plane of one FOP, recomputing the planes
- * from the FOP (no plane is stored):
- *   lse[k-1] = log sum_{i,j} exp(HP_k(i,j) / tau)            (fp32 out)
- * hs_lse_backward overwrites dfop [N_temp][N_chan] fp32 with gscale times
- * the gradient of L = sum_k tau * lse[k-1] with respect to the FOP (unscaled
- * units), given the lse values of the forward call.  Both need `work` of
- * hs_lse_workspace_bytes(plan) bytes. */
+/* Log-sum-exp statistic of each plane of one FOP (tau > 0):
+ *   lse[k-1] = log sum_{i,j} exp(HP_k(i,j) / tau)        ([n_hp] fp64, device)
+ * formed with a running maximum and a fixed-order two-level reduction
+ * (deterministic).  hs_lse_backward overwrites dfop [N_temp][N_chan] fp32
+ * with gscale times the gradient of L = sum_k tau * lse[k-1] with respect to
+ * the FOP (unscaled units): the weights exp(HP_k / tau - lse[k-1]) taken
+ * through hs_sum_backward.  Both materialise the planes in `work`, which
+ * must hold hs_lse_workspace_bytes(plan) bytes.  Single-FOP plans only. */
 size_t hs_lse_workspace_bytes(const hs_plan* plan);
-hs_status hs_lse_forward(const hs_plan* plan, const void* fop, int64_t ld, float tau, float* lse,
+hs_status hs_lse_forward(const hs_plan* plan, const void* fop, int64_t ld, float tau, double* lse,
                          void* work, void* stream);
-hs_status hs_lse_backward(const hs_plan* plan, const void* fop, int64_t ld, const float* lse,
+hs_status hs_lse_backward(const hs_plan* plan, const void* fop, int64_t ld, const double* lse,
                           float tau, float gscale, float* dfop, void* work, void* stream);
 
 /* Host check of counts copied back from hs_detect: HS_ERR_OVERFLOW when

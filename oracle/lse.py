@@ -47,3 +47,24 @@ def grad_fop_f64(S, tau, gscale=1.0):
     """dL/dFOP (times gscale) from fp32-or-fp64 planes S of that FOP."""
     w = weights_f64(S, tau)
     return vjp_f64(w * gscale)
+
+
+def grad_point_f64(S, lse, tau, a, b, gscale=1.0):
+    """dL/dFOP at one FOP point (storage row a, bin b), gscale times the
+    gradient of L = sum_k tau * LSE_k, from the planes S [H][T][N] and their
+    LSE (both promoted to fp64).  Transpose of Eq. 1 written out: the point
+    feeds every (r, j) with floor((r - c)/m) + c = a and floor(j/m) = b, for
+    m = 1..H, in planes k >= m; c = T // 2.  Only that m x m box of weights
+    is evaluated, so this serves sampled checks on full-size planes."""
+    H, T, N = S.shape
+    c = T // 2
+    total = 0.0
+    for m in range(1, H + 1):
+        r_lo, r_hi = max(c + m * (a - c), 0), min(c + m * (a - c) + m - 1, T - 1)
+        j_lo, j_hi = m * b, min(m * b + m - 1, N - 1)
+        if r_lo > r_hi or j_lo > j_hi:
+            continue
+        for k in range(m, H + 1):
+            box = np.asarray(S[k - 1, r_lo:r_hi + 1, j_lo:j_hi + 1], dtype=np.float64)
+            total += np.exp(box / tau - lse[k - 1]).sum()
+    return gscale * total

@@ -279,6 +279,85 @@ class Plan:
         hs_detect(self.handle, fop, ld, ta, out, capacity, counts, stream)
         return out, counts
 
+    def _work(self, nbytes, device):
+        return torch.empty(max(int(nbytes), 1), dtype=torch.uint8, device=device)
+
+    def backward(self, g, dfop=None, stream=None):
+        """dL/dFOP [T][N] fp32 from g = dL/dHP [H][T][N] fp32 (hs_sum_backward)."""
+        if g.dtype != torch.float32 or tuple(g.shape) != (self.n_hp, self.n_temp, self.n_chan) \
+                or not g.is_contiguous():
+            raise ValueError("g must be a contiguous [n_hp][n_temp][n_chan] fp32 tensor")
+        if dfop is None:
+            dfop = torch.empty((self.n_temp, self.n_chan), dtype=torch.float32, device=g.device)
+        work = self._work(hs_backward_workspace_bytes(self.handle), g.device)
+        hs_sum_backward(self.handle, g, dfop, work, stream)
+        return dfop
+
+    def lse(self, fop, tau, stream=None):
+        """[H] fp64 tensor: log sum exp(HP_k / tau) over each plane."""
+        ld = self._fop(fop)
+        out = torch.empty(self.n_hp, dtype=torch.float64, device=fop.device)
+        work = self._work(hs_lse_workspace_bytes(self.handle), fop.device)
+        hs_lse_forward(self.handle, fop, ld, tau, out, work, stream)
+        return out
+
+    def lse_backward(self, fop, lse, tau, gscale=1.0, dfop=None, stream=None):
+        """gscale * dL/dFOP for L = sum_k tau * lse_k, [T][N] fp32."""
+        ld = self._fop(fop)
+        if dfop is None:
+            dfop = torch.empty((self.n_temp, self.n_chan), dtype=torch.float32, device=fop.device)
+        work = self._work(hs_lse_workspace_bytes(self.handle), fop.device)
+        hs_lse_backward(self.handle, fop, ld, lse, tau, gscale, dfop, work, stream)
+        return dfop
+
+
+def sort_candidates(out, n, stream=None):
+    """Sort the first n rows of a detect output ([cap][2] int32) in place into
+    ascending CL1 order."""
+    n = int(n)
+    if n > 1:
+        work = torch.empty(max(hs_sort_workspace_bytes(n), 1), dtype=torch.uint8, device=out.device)
+        hs_sort_candidates(out, n, work, stream)
+    return out
+
+
+class HarmonicSum(torch.autograd.Function):
+    """planes = HarmonicSum.apply(fop, plan): all H planes of an fp32 FOP
+    (hs_sum); the backward is the hand-written transpose (hs_sum_backward)."""
+
+    @staticmethod
+    def forward(ctx, fop, plan):
+        if plan.dtype != 0:
+            raise ValueError("autograd needs an fp32 plan")
+        ctx.plan = plan
+        return plan.sum(fop)
+
+    @staticmethod
+    def backward(ctx, g):
+        return ctx.plan.backward(g.contiguous().float()), None
+
+
+class HarmonicLSE(torch.autograd.Function):
+    """loss = HarmonicLSE.apply(fop, plan, tau): L = sum_k tau * log sum
+    exp(HP_k / tau) over the planes of one fp32 FOP (fp64 scalar).  The
+    backward recomputes the planes and takes the weights through the
+    transpose (hs_lse_backward)."""
+
+    @staticmethod
+    def forward(ctx, fop, plan, tau):
+        if plan.dtype != 0:
+            raise ValueError("autograd needs an fp32 plan")
+        lse = plan.lse(fop, tau)
+        ctx.save_for_backward(fop, lse)
+        ctx.plan, ctx.tau = plan, float(tau)
+        return (lse * ctx.tau).sum()
+
+    @staticmethod
+    def backward(ctx, gL):
+        fop, lse = ctx.saved_tensors
+        g = float(gL)
+        return ctx.plan.lse_backward(fop, lse, ctx.tau, gscale=g), None, None
+
 
 def split_candidates(out, n):
     """(word uint32 numpy, power float32 numpy) of the first n entries of `out`."""

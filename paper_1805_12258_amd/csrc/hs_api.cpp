@@ -3,6 +3,7 @@
 // returns an hs_status and catches C++ exceptions before they reach the ABI.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <new>
@@ -158,11 +159,11 @@ hs_status hs_plan_destroy(hs_plan* p)
     bool have_dev = hipGetDevice(&cur) == hipSuccess;
     for (int dev = 0; dev < 64; ++dev) {
         if (p->d_tables[dev]) {
-            if (have_dev) hipSetDevice(dev);
-            hipFree(p->d_tables[dev]);
+            if (have_dev) (void)hipSetDevice(dev);
+            (void)hipFree(p->d_tables[dev]);
         }
     }
-    if (have_dev && cur >= 0) hipSetDevice(cur);
+    if (have_dev && cur >= 0) (void)hipSetDevice(cur);
     delete p;
     return HS_OK;
 }
@@ -254,7 +255,7 @@ hs_status hs_detect_batched(const hs_plan* p, const void* const* fops, const int
                 int64_t* d = nullptr;
                 if (hipMalloc(&d, n * sizeof(int64_t)) != hipSuccess) return HS_ERR_NOMEM;
                 if (hipMemcpy(d, h.data(), n * sizeof(int64_t), hipMemcpyHostToDevice) != hipSuccess) {
-                    hipFree(d);
+                    (void)hipFree(d);
                     return HS_ERR_HIP;
                 }
                 p->d_tables[dev] = d;
@@ -293,37 +294,102 @@ hs_status hs_detect_batched(const hs_plan* p, const void* const* fops, const int
     }
 }
 
-size_t hs_sort_workspace_bytes(int64_t n) { return n > 0 ? (size_t)n * 16 + 4096 : 0; }
+size_t hs_sort_workspace_bytes(int64_t n)
+{
+    if (n <= 1) return 0;
+    size_t bytes = 0;
+    if (hsk::sort_workspace(n, &bytes) != hipSuccess) return 0;
+    return bytes;
+}
 
 hs_status hs_sort_candidates(hs_cand* cand, int64_t n, void* work, void* stream)
 {
-    (void)cand; (void)n; (void)work; (void)stream;
-    return HS_ERR_UNSUPPORTED;
+    if (n < 0 || (n > 1 && (!cand || !work))) return HS_ERR_INVALID;
+    try {
+        return from_hip(hsk::sort_candidates(reinterpret_cast<uint64_t*>(cand), n, work,
+                                             (hipStream_t)stream));
+    } catch (...) {
+        return HS_ERR_HIP;
+    }
 }
 
-size_t hs_backward_workspace_bytes(const hs_plan* p) { (void)p; return 0; }
+namespace {
+size_t round256(size_t x) { return (x + 255) & ~(size_t)255; }
+size_t plane_bytes(const hs_plan* p) { return (size_t)p->T * (size_t)p->N * 4; }
+size_t partial_bytes(const hs_plan* p)
+{
+    return (size_t)hsk::backward_partial_floats((int)p->T, p->H, p->tile_rows, p->N) * 4;
+}
+bool tau_ok(float tau) { return tau > 0.0f && tau < INFINITY; }
+}  // namespace
+
+size_t hs_backward_workspace_bytes(const hs_plan* p)
+{
+    if (!p || p->n_fops != 0) return 0;
+    return round256(partial_bytes(p));
+}
 
 hs_status hs_sum_backward(const hs_plan* p, const float* g, float* dfop, void* work, void* stream)
 {
-    (void)p; (void)g; (void)dfop; (void)work; (void)stream;
-    return HS_ERR_UNSUPPORTED;
+    if (!p || p->n_fops != 0 || !g || !dfop) return HS_ERR_INVALID;
+    if (partial_bytes(p) > 0 && !work) return HS_ERR_INVALID;
+    try {
+        return from_hip(hsk::launch_backward(g, dfop, static_cast<float*>(work), (int)p->T, p->N, p->H,
+                                             p->tile_rows, (hipStream_t)stream));
+    } catch (...) {
+        return HS_ERR_HIP;
+    }
 }
 
-size_t hs_lse_workspace_bytes(const hs_plan* p) { (void)p; return 0; }
+// Workspace of the statistic: the H planes, then the larger of the backward
+// partials and the reduction's per-block pairs.
+size_t hs_lse_workspace_bytes(const hs_plan* p)
+{
+    if (!p || p->n_fops != 0) return 0;
+    const size_t tail = std::max(partial_bytes(p), (size_t)hsk::lse_part_bytes(p->H));
+    return round256(plane_bytes(p) * p->H) + round256(tail);
+}
 
-hs_status hs_lse_forward(const hs_plan* p, const void* fop, int64_t ld, float tau, float* lse,
+hs_status hs_lse_forward(const hs_plan* p, const void* fop, int64_t ld, float tau, double* lse,
                          void* work, void* stream)
 {
-    (void)p; (void)fop; (void)ld; (void)tau; (void)lse; (void)work; (void)stream;
-    return HS_ERR_UNSUPPORTED;
+    if (!p || p->n_fops != 0 || !lse || !work || !tau_ok(tau)) return HS_ERR_INVALID;
+    if (!fop_ok(p, fop, ld, p->N)) return HS_ERR_INVALID;
+    try {
+        hipStream_t s = (hipStream_t)stream;
+        float* planes = static_cast<float*>(work);
+        void* tail = static_cast<char*>(work) + round256(plane_bytes(p) * p->H);
+        hsk::TileArgs a = tile_args(p, fop, ld);
+        a.hp = planes;
+        hipError_t e = hsk::launch_fused(hsk::kModeSum, p->dtype, p->H, a, p->tiles_total,
+                                         persistent_grid(p, p->tiles_total), p->lds_bytes, s);
+        if (e != hipSuccess) return HS_ERR_HIP;
+        return from_hip(hsk::launch_lse_reduce(planes, p->T * p->N, p->H, tau, tail, lse, s));
+    } catch (...) {
+        return HS_ERR_HIP;
+    }
 }
 
-hs_status hs_lse_backward(const hs_plan* p, const void* fop, int64_t ld, const float* lse,
+hs_status hs_lse_backward(const hs_plan* p, const void* fop, int64_t ld, const double* lse,
                           float tau, float gscale, float* dfop, void* work, void* stream)
 {
-    (void)p; (void)fop; (void)ld; (void)lse; (void)tau; (void)gscale; (void)dfop; (void)work;
-    (void)stream;
-    return HS_ERR_UNSUPPORTED;
+    if (!p || p->n_fops != 0 || !lse || !dfop || !work || !tau_ok(tau)) return HS_ERR_INVALID;
+    if (!fop_ok(p, fop, ld, p->N)) return HS_ERR_INVALID;
+    try {
+        hipStream_t s = (hipStream_t)stream;
+        float* planes = static_cast<float*>(work);
+        float* part = reinterpret_cast<float*>(static_cast<char*>(work) + round256(plane_bytes(p) * p->H));
+        hsk::TileArgs a = tile_args(p, fop, ld);
+        a.hp = planes;
+        hipError_t e = hsk::launch_fused(hsk::kModeSum, p->dtype, p->H, a, p->tiles_total,
+                                         persistent_grid(p, p->tiles_total), p->lds_bytes, s);
+        if (e != hipSuccess) return HS_ERR_HIP;
+        e = hsk::launch_lse_weights(planes, p->T * p->N, p->H, tau, lse, gscale, s);
+        if (e != hipSuccess) return HS_ERR_HIP;
+        return from_hip(hsk::launch_backward(planes, dfop, part, (int)p->T, p->N, p->H, p->tile_rows, s));
+    } catch (...) {
+        return HS_ERR_HIP;
+    }
 }
 
 hs_status hs_check_counts(const int64_t* counts_host, int32_t n_hp, int64_t capacity)

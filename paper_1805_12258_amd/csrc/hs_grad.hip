@@ -1,0 +1,280 @@
+// Transpose of the plane map (the vector-Jacobian product of Eq. 1-2) and
+// the log-sum-exp statistic built on it.
+//
+// Backward.  With G_m = sum_{k >= m} g_k (suffix sums over the planes),
+//     dFOP(a, b) = sum_m  sum_{(r, j) : src(r, m) = a, floor(j/m) = b}  G_m(r, j),
+// where src(r, m) = floor((r - c)/m) + c is the source row of Eq. 1.  The
+// preimage of (a, b) under m is an m x m box of plane points (clipped to the
+// plane).  Two deterministic passes, no floating-point atomics:
+//   1. per tile of 32 rows x 256 bins: read g_H .. g_1 once (coalesced), form
+//      the suffix sums in registers, write G_1 to dFOP, and for m >= 2 stage
+//      G_m in LDS and sum each target's box inside the tile (fixed order) into
+//      a per-(m, tile) partial rectangle in the workspace;
+//   2. per dFOP point: add, for m = 2..H in order, the (at most 4) tile
+//      partials that cover it.
+// The same input gives bitwise the same output.
+//
+// Log-sum-exp.  lse_k = log sum_{i,j} exp(HP_k(i,j) / tau) per plane, with a
+// running maximum (each term exp(x - M) <= 1) and a fixed two-level
+// reduction; lse is returned in fp64 so that the weights
+// exp(HP_k / tau - lse_k) of the backward keep fp32 accuracy even where
+// |lse| is large.
+#include <hip/hip_runtime.h>
+
+#include "hs_internal.h"
+
+namespace hsk {
+
+namespace {
+
+constexpr int kGThreads = 512;
+
+__device__ __forceinline__ int src_row(int r, int m, int c)
+{
+    return floordiv32(r - c, m) + c;
+}
+
+// Offset (in floats) of the partial rectangles of stretch factor m.
+__host__ __device__ inline int64_t partial_offset(int m, int row_blocks, int64_t n_bt)
+{
+    int64_t o = 0;
+    for (int k = 2; k < m; ++k)
+        o += (int64_t)row_blocks * stage_rows(k) * n_bt * stage_pitch(k);
+    return o;
+}
+
+// Pass 1: one block per tile (rb, bt).
+__global__ __launch_bounds__(kGThreads) void k_bwd_tiles(const float* __restrict__ g, float* __restrict__ dfop,
+                                                         float* __restrict__ part, int T, int N, int H,
+                                                         int R, int row_blocks, int n_bt)
+{
+    __shared__ float tile[kMaxTileRows * kTileBins];
+    const int rb = blockIdx.x / n_bt;
+    const int bt = blockIdx.x - rb * n_bt;
+    const int r0 = rb * R;
+    const int nr = min(R, T - r0);
+    const int j0 = bt * kTileBins;
+    const int nb = min(kTileBins, N - j0);
+    const int c = T / 2;
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int64_t plane = (int64_t)T * N;
+
+    float s[kRowsPerWave][kV];
+#pragma unroll
+    for (int q = 0; q < kRowsPerWave; ++q)
+#pragma unroll
+        for (int v = 0; v < kV; ++v) s[q][v] = 0.0f;
+
+    for (int m = H; m >= 1; --m) {
+        // suffix sum G_m = g_m + G_{m+1} at the thread's points
+#pragma unroll
+        for (int q = 0; q < kRowsPerWave; ++q) {
+            const int rr = wave + kWaves * q;
+            if (rr >= nr) continue;
+            const float* src = g + (int64_t)(m - 1) * plane + (int64_t)(r0 + rr) * N + j0;
+#pragma unroll
+            for (int v = 0; v < kV; ++v) {
+                const int jj = kV * lane + v;
+                if (jj < nb) s[q][v] = src[jj] + s[q][v];
+            }
+        }
+        if (m == 1) {
+#pragma unroll
+            for (int q = 0; q < kRowsPerWave; ++q) {
+                const int rr = wave + kWaves * q;
+                if (rr >= nr) continue;
+                float* dst = dfop + (int64_t)(r0 + rr) * N + j0;
+#pragma unroll
+                for (int v = 0; v < kV; ++v) {
+                    const int jj = kV * lane + v;
+                    if (jj < nb) dst[jj] = s[q][v];
+                }
+            }
+            break;
+        }
+        __syncthreads();               // the previous factor's gathers are done
+#pragma unroll
+        for (int q = 0; q < kRowsPerWave; ++q) {
+            const int rr = wave + kWaves * q;
+#pragma unroll
+            for (int v = 0; v < kV; ++v) tile[rr * kTileBins + kV * lane + v] = s[q][v];
+        }
+        __syncthreads();
+        // every target cell of the tile for factor m: rows src(r0, m) + tr,
+        // bins floor(j0/m) + tc; its box inside this tile, summed row by row
+        const int NR = stage_rows(m), P = stage_pitch(m);
+        const int lo = src_row(r0, m, c);
+        const int blo = j0 / m;
+        float* out = part + partial_offset(m, row_blocks, n_bt) +
+                     (((int64_t)rb * NR) * n_bt + bt) * P;
+        for (int e = threadIdx.x; e < NR * P; e += kGThreads) {
+            const int tr = e / P, tc = e - tr * P;
+            const int a = lo + tr, b = blo + tc;
+            const int ra = max(c + m * (a - c), r0), rz = min(c + m * (a - c) + m - 1, r0 + nr - 1);
+            const int ja = max(m * b, j0), jz = min(m * b + m - 1, j0 + nb - 1);
+            float acc = 0.0f;
+            for (int r = ra; r <= rz; ++r)
+                for (int j = ja; j <= jz; ++j) acc += tile[(r - r0) * kTileBins + (j - j0)];
+            out[(int64_t)tr * n_bt * P + tc] = acc;
+        }
+    }
+}
+
+// Pass 2: dFOP(a, b) += sum over m = 2..H of the partials covering (a, b).
+__global__ __launch_bounds__(256) void k_bwd_reduce(float* __restrict__ dfop, const float* __restrict__ part,
+                                                    int T, int N, int H, int R, int row_blocks, int n_bt)
+{
+    const int c = T / 2;
+    const int64_t total = (int64_t)T * N;
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        const int a = (int)(e / N), b = (int)(e - (int64_t)a * N);
+        float acc = dfop[e];
+        for (int m = 2; m <= H; ++m) {
+            const int first = max(c + m * (a - c), 0), last = min(c + m * (a - c) + m - 1, T - 1);
+            if (first > last || (int64_t)m * b > N - 1) continue;
+            const int jb0 = m * b, jb1 = min(m * b + m - 1, N - 1);
+            const int NR = stage_rows(m), P = stage_pitch(m);
+            const float* pm = part + partial_offset(m, row_blocks, n_bt);
+            float pmsum = 0.0f;
+            for (int rb = first / R; rb <= last / R; ++rb) {
+                const int tr = a - src_row(rb * R, m, c);
+                for (int bt = jb0 / kTileBins; bt <= jb1 / kTileBins; ++bt) {
+                    const int tc = b - (bt * kTileBins) / m;
+                    pmsum += pm[(((int64_t)rb * NR + tr) * n_bt + bt) * P + tc];
+                }
+            }
+            acc += pmsum;
+        }
+        dfop[e] = acc;
+    }
+}
+
+// Log-sum-exp, level 1: block (k, i) reduces a contiguous chunk of plane k
+// to a (max, sum of exp(x - max)) pair, x = HP / tau evaluated in fp64.
+constexpr int kLseBlocks = 256;
+
+__device__ __forceinline__ void lse_merge(double& M, float& S, double M2, float S2)
+{
+    if (S2 == 0.0f) return;
+    if (S == 0.0f) { M = M2; S = S2; return; }
+    if (M2 > M) { S = S * expf((float)(M - M2)) + S2; M = M2; }
+    else S = S + S2 * expf((float)(M2 - M));
+}
+
+__global__ __launch_bounds__(256) void k_lse_part(const float* __restrict__ hp, int64_t plane, double inv_tau,
+                                                  double* __restrict__ pm, float* __restrict__ ps)
+{
+    const int k = blockIdx.y;
+    const int64_t chunk = (plane + gridDim.x - 1) / gridDim.x;
+    const int64_t beg = blockIdx.x * chunk, end = min(plane, beg + chunk);
+    const float* x = hp + (int64_t)k * plane;
+    double M = 0.0;
+    float S = 0.0f;
+    for (int64_t e = beg + threadIdx.x; e < end; e += blockDim.x) {
+        const double xd = (double)x[e] * inv_tau;
+        if (S == 0.0f) { M = xd; S = 1.0f; }
+        else if (xd > M) { S = S * expf((float)(M - xd)) + 1.0f; M = xd; }
+        else S += expf((float)(xd - M));
+    }
+    __shared__ double sm[256];
+    __shared__ float ss[256];
+    sm[threadIdx.x] = M;
+    ss[threadIdx.x] = S;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (threadIdx.x < w) {
+            double m1 = sm[threadIdx.x];
+            float s1 = ss[threadIdx.x];
+            lse_merge(m1, s1, sm[threadIdx.x + w], ss[threadIdx.x + w]);
+            sm[threadIdx.x] = m1;
+            ss[threadIdx.x] = s1;
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        pm[(int64_t)k * gridDim.x + blockIdx.x] = sm[0];
+        ps[(int64_t)k * gridDim.x + blockIdx.x] = ss[0];
+    }
+}
+
+// Level 2: one thread per plane merges the block pairs in block order.
+__global__ void k_lse_final(const double* __restrict__ pm, const float* __restrict__ ps, int H, int nblk,
+                            double* __restrict__ lse)
+{
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= H) return;
+    double M = 0.0;
+    float S = 0.0f;
+    for (int i = 0; i < nblk; ++i) lse_merge(M, S, pm[(int64_t)k * nblk + i], ps[(int64_t)k * nblk + i]);
+    lse[k] = M + log((double)S);
+}
+
+// Weights of L = sum_k tau * lse_k: dL/dHP_k = exp(HP_k / tau - lse_k), times gscale.
+__global__ __launch_bounds__(256) void k_lse_weights(float* __restrict__ hp, int64_t plane, int H, double inv_tau,
+                                                     const double* __restrict__ lse, float gscale)
+{
+    const int64_t total = plane * H;
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        const int k = (int)(e / plane);
+        const double d = (double)hp[e] * inv_tau - lse[k];
+        hp[e] = gscale * expf((float)d);
+    }
+}
+
+int grid_for(int64_t n, int threads, int cap)
+{
+    const int64_t b = (n + threads - 1) / threads;
+    return (int)(b < cap ? (b < 1 ? 1 : b) : cap);
+}
+
+}  // namespace
+
+int64_t backward_partial_floats(int T, int H, int R, int64_t N)
+{
+    const int row_blocks = (T + R - 1) / R;
+    const int64_t n_bt = (N + kTileBins - 1) / kTileBins;
+    return partial_offset(H + 1, row_blocks, n_bt);
+}
+
+hipError_t launch_backward(const float* g, float* dfop, float* part, int T, int64_t N, int H, int R,
+                           hipStream_t s)
+{
+    const int row_blocks = (T + R - 1) / R;
+    const int n_bt = (int)((N + kTileBins - 1) / kTileBins);
+    const int64_t tiles = (int64_t)row_blocks * n_bt;
+    if (tiles > 0x7fffffff) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_bwd_tiles, dim3((unsigned)tiles), dim3(kGThreads), 0, s, g, dfop, part, T,
+                       (int)N, H, R, row_blocks, n_bt);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_bwd_reduce, dim3(grid_for((int64_t)T * N, 256, 65536)), dim3(256), 0, s, dfop,
+                       part, T, (int)N, H, R, row_blocks, n_bt);
+    return hipGetLastError();
+}
+
+int64_t lse_part_bytes(int H) { return (int64_t)H * kLseBlocks * (8 + 4); }
+
+hipError_t launch_lse_reduce(const float* hp, int64_t plane, int H, double tau, void* work, double* lse,
+                             hipStream_t s)
+{
+    double* pm = static_cast<double*>(work);
+    float* ps = reinterpret_cast<float*>(pm + (int64_t)H * kLseBlocks);
+    hipLaunchKernelGGL(k_lse_part, dim3(kLseBlocks, H), dim3(256), 0, s, hp, plane, 1.0 / tau, pm, ps);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_lse_final, dim3(1), dim3(64), 0, s, pm, ps, H, kLseBlocks, lse);
+    return hipGetLastError();
+}
+
+hipError_t launch_lse_weights(float* hp, int64_t plane, int H, double tau, const double* lse, float gscale,
+                              hipStream_t s)
+{
+    hipLaunchKernelGGL(k_lse_weights, dim3(grid_for(plane * H, 256, 65536)), dim3(256), 0, s, hp, plane, H,
+                       1.0 / tau, lse, gscale);
+    return hipGetLastError();
+}
+
+}  // namespace hsk

@@ -178,6 +178,20 @@ hipError_t launch_batched(int dtype, int H, const BatchArgs& a, int grid, int ld
                           hipStream_t s);
 hipError_t launch_zero_i64(int64_t* p, int64_t n, hipStream_t s);
 
+// Transpose of the plane map and the log-sum-exp statistic (hs_grad.hip).
+int64_t backward_partial_floats(int T, int H, int R, int64_t N);
+hipError_t launch_backward(const float* g, float* dfop, float* part, int T, int64_t N, int H, int R,
+                           hipStream_t s);
+int64_t lse_part_bytes(int H);
+hipError_t launch_lse_reduce(const float* hp, int64_t plane, int H, double tau, void* work, double* lse,
+                             hipStream_t s);
+hipError_t launch_lse_weights(float* hp, int64_t plane, int H, double tau, const double* lse, float gscale,
+                              hipStream_t s);
+
+// Canonical candidate order (hs_sort.hip).
+hipError_t sort_workspace(int64_t n, size_t* bytes);
+hipError_t sort_candidates(uint64_t* cand, int64_t n, void* work, hipStream_t s);
+
 }  // namespace hsk
 
 struct hs_plan {

@@ -369,3 +369,18 @@ def test_lse_gradient_finite_differences():
         xm = x.copy(); xm[a, b] -= eps
         fd = (L(xp) - L(xm)) / (2 * eps)
         assert abs(fd - g[a, b]) <= 1e-4 * gmax + 1e-3 * abs(g[a, b]), (a, b, fd, g[a, b])
+
+
+def test_lse_point_gradient_equals_plane_gradient():
+    """The per-point transpose (box sums of the weights) equals the scatter
+    form of the whole-plane gradient at every point of a small plane."""
+    from oracle import lse
+    rng = np.random.default_rng(14)
+    T, N, H, tau = 11, 97, 6, 0.5
+    x = rng.exponential(1.0, size=(T, N)).astype(np.float32)
+    S = oracle.sum_f32(x, H)
+    g = lse.grad_fop_f64(S, tau, gscale=1.5)
+    L = lse.lse_f64(S, tau)
+    for a in range(T):
+        for b in range(0, N, 7):
+            assert lse.grad_point_f64(S, L, tau, a, b, gscale=1.5) == pytest.approx(g[a, b], rel=1e-12)
