@@ -27,7 +27,11 @@ namespace hsk {
 
 namespace {
 
-constexpr int kGThreads = 512;
+// Pass 1 tiles are kMaxTileRows x kTileBins like the forward's, covered by
+// 8 waves of 4 rows each.
+constexpr int kGWaves = 8;
+constexpr int kGRows = kMaxTileRows / kGWaves;
+constexpr int kGThreads = kGWaves * kLanes;
 
 __device__ __forceinline__ int src_row(int r, int m, int c)
 {
@@ -60,17 +64,17 @@ __global__ __launch_bounds__(kGThreads) void k_bwd_tiles(const float* __restrict
     const int wave = threadIdx.x >> 6;
     const int64_t plane = (int64_t)T * N;
 
-    float s[kRowsPerWave][kV];
+    float s[kGRows][kV];
 #pragma unroll
-    for (int q = 0; q < kRowsPerWave; ++q)
+    for (int q = 0; q < kGRows; ++q)
 #pragma unroll
         for (int v = 0; v < kV; ++v) s[q][v] = 0.0f;
 
     for (int m = H; m >= 1; --m) {
         // suffix sum G_m = g_m + G_{m+1} at the thread's points
 #pragma unroll
-        for (int q = 0; q < kRowsPerWave; ++q) {
-            const int rr = wave + kWaves * q;
+        for (int q = 0; q < kGRows; ++q) {
+            const int rr = wave + kGWaves * q;
             if (rr >= nr) continue;
             const float* src = g + (int64_t)(m - 1) * plane + (int64_t)(r0 + rr) * N + j0;
 #pragma unroll
@@ -81,8 +85,8 @@ __global__ __launch_bounds__(kGThreads) void k_bwd_tiles(const float* __restrict
         }
         if (m == 1) {
 #pragma unroll
-            for (int q = 0; q < kRowsPerWave; ++q) {
-                const int rr = wave + kWaves * q;
+            for (int q = 0; q < kGRows; ++q) {
+                const int rr = wave + kGWaves * q;
                 if (rr >= nr) continue;
                 float* dst = dfop + (int64_t)(r0 + rr) * N + j0;
 #pragma unroll
@@ -95,8 +99,8 @@ __global__ __launch_bounds__(kGThreads) void k_bwd_tiles(const float* __restrict
         }
         __syncthreads();               // the previous factor's gathers are done
 #pragma unroll
-        for (int q = 0; q < kRowsPerWave; ++q) {
-            const int rr = wave + kWaves * q;
+        for (int q = 0; q < kGRows; ++q) {
+            const int rr = wave + kGWaves * q;
 #pragma unroll
             for (int v = 0; v < kV; ++v) tile[rr * kTileBins + kV * lane + v] = s[q][v];
         }
