@@ -1,7 +1,7 @@
 """Benchmark: fused harmonic summing + detection on one MI355X.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-variants]
-                    [--batched N_FOPS] [--copy-calibration]
+                    [--batched-fops N] [--copy-calibration]
 
 Workload: one filter-output plane of 85 templates x 2^21 bins of fp32 power
 (Exp(1) noise, 50 injected harmonic signals, seed 2), 8 harmonic planes,
@@ -118,6 +118,92 @@ def cpu_baseline(fop_cpu, H, ta_np, max_bins, min_seconds=10.0):
                          one.size / dt1)}
 
 
+def candidate_words(out, counts):
+    """Sorted int64 CL1 words of a detect output (first counts[-1] rows)."""
+    n = int(counts[-1].item())
+    w = out[:n, 0].to(torch.int64) & 0xffffffff
+    return torch.sort(w).values
+
+
+def precision_recall(words, ref_words):
+    """Candidate-set agreement of a reduced-precision run with the fp32 run
+    (which equals the oracle bitwise)."""
+    if len(words) == 0 or len(ref_words) == 0:
+        return 1.0 if len(words) == len(ref_words) else 0.0, 0.0
+    common = int(torch.isin(words, ref_words).sum().item())
+    return common / len(words), common / len(ref_words)
+
+
+def batched_leg(n_fops, steps, warmup, dev):
+    """The batched workload: n_fops FOPs of 85 templates and 2^19, 2^20 or
+    2^21 bins (seeded), 16 planes, in one persistent launch replayed from a
+    captured HIP graph, against one hs_detect launch per FOP."""
+    import paper_1805_12258_amd as hs
+    import synth
+    cfg = synth.BATCHED
+    T, H = cfg["n_temp"], cfg["n_hp"]
+    lens = synth.batched_lengths(n_fops)
+    fops = [synth.make_batched_fop(f, n, device=dev) for f, n in enumerate(lens)]
+    ta = torch.from_numpy(synth.thresholds(H, T)).to(dev)
+    # room for twice the expected noise candidates of 16 planes
+    caps = [int(2 * 180000 * n / (1 << 20)) + 4096 for n in lens]
+    offs = np.concatenate([[0], np.cumsum(caps)[:-1]]).astype(np.int64)
+    out = torch.empty((int(np.sum(caps)), 2), dtype=torch.int32, device=dev)
+    counts = torch.empty((n_fops, H + 1), dtype=torch.int64, device=dev)
+    fop_ptrs = torch.tensor([x.data_ptr() for x in fops], dtype=torch.int64, device=dev)
+    lds = torch.tensor([x.stride(0) for x in fops], dtype=torch.int64, device=dev)
+    offs_d = torch.from_numpy(offs).to(dev)
+    caps_d = torch.tensor(caps, dtype=torch.int64, device=dev)
+    plan = hs.Plan(T, 0, H, n_chans=lens)
+    args = (plan.handle, fop_ptrs, lds, ta, out, offs_d, caps_d, counts)
+    hs.hs_detect_batched(*args)                 # eager call: uploads the plan tables
+    torch.cuda.synchronize()
+    stream = torch.cuda.Stream()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph, stream=stream):
+        hs.hs_detect_batched(*args, stream=stream)
+    for _ in range(warmup):
+        graph.replay()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(steps):
+        graph.replay()
+    e1.record()
+    torch.cuda.synchronize()
+    batched_ms = e0.elapsed_time(e1) / steps
+    batched_counts = counts.clone()
+
+    plans = {n: hs.Plan(T, n, H) for n in sorted(set(lens))}
+    single_counts = torch.empty_like(counts)
+
+    def per_fop():
+        for f, x in enumerate(fops):
+            hs.hs_detect(plans[lens[f]].handle, x, x.stride(0), ta, out[offs[f]:], caps[f],
+                         single_counts[f])
+
+    for _ in range(max(1, warmup // 2)):
+        per_fop()
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(steps):
+        per_fop()
+    e1.record()
+    torch.cuda.synchronize()
+    single_ms = e0.elapsed_time(e1) / steps
+    if not torch.equal(single_counts, batched_counts):
+        raise RuntimeError("batched and per-FOP candidate counts differ")
+    points = T * int(np.sum(lens))
+    fop_bytes = 4 * points
+    del fops, out
+    return {"n_fops": n_fops, "points": points, "fop_gb": fop_bytes / 1e9,
+            "value": points / (batched_ms * 1e-3), "unit": "points/s",
+            "ms_per_step": batched_ms, "hbm_gbs": fop_bytes / (batched_ms * 1e-3) / 1e9,
+            "per_fop_launches_ms": single_ms, "vs_per_fop": single_ms / batched_ms,
+            "candidates": int(batched_counts[:, -1].sum().item()),
+            "launch": "one persistent kernel replayed from a captured HIP graph"}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -126,6 +212,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-variants", action="store_true")
     ap.add_argument("--cpu-bins", type=int, default=1 << 21)
+    ap.add_argument("--batched-fops", type=int, default=512,
+                    help="FOPs of the batched leg (0 skips it)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one plain device copy of the FOP's size (counter scale)")
     args = ap.parse_args()
@@ -155,6 +243,8 @@ def main():
         del dst
 
     r = time_detect(plan, fop, ta, capacity, args.steps, args.warmup)
+    ref_out, ref_counts = plan.detect(fop, ta, capacity=capacity)
+    ref_words = candidate_words(ref_out, ref_counts)
     points = T * N
     n_cand = int(r["counts"][-1])
     alg_bytes = points * 4 + 8 * n_cand + 8 * (H + 1)
@@ -194,14 +284,25 @@ def main():
             store = synth.quantize(fop, dt, scale)
             p2 = hs.Plan(T, N, H, dtype=name, input_scale=scale)
             r2 = time_detect(p2, store, ta, capacity, max(20, args.steps // 2), 5)
+            o2, c2 = p2.detect(store, ta, capacity=capacity)
+            prec, rec = precision_recall(candidate_words(o2, c2), ref_words)
             ab = points * 2 + 8 * int(r2["counts"][-1]) + 8 * (H + 1)
             var[name] = {"value": points / (r2["ms_per_step"] * 1e-3),
                          "ms_per_step": r2["ms_per_step"], "launch_ms": r2["launch_ms"],
                          "hbm_gbs": ab / (r2["launch_ms"] * 1e-3) / 1e9,
                          "vs_f32": r["ms_per_step"] / r2["ms_per_step"],
-                         "candidates": int(r2["counts"][-1])}
+                         "candidates": int(r2["counts"][-1]),
+                         "precision_vs_f32": prec, "recall_vs_f32": rec,
+                         "storage": "%s of power x %g, fp32 sums" % (name, scale)}
             del store
         line["variants"] = var
+
+    if args.batched_fops > 0:
+        del fop, ref_out
+        torch.cuda.empty_cache()
+        line["batched"] = batched_leg(args.batched_fops, max(3, args.steps // 40),
+                                      2, dev)
+        fop = synth.make_ska(device=dev)
 
     if not args.no_cpu:
         fop_cpu = fop[:, :args.cpu_bins].cpu()
