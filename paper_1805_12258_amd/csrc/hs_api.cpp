@@ -123,13 +123,13 @@ hs_status hs_plan_create(hs_plan** out, const hs_plan_desc* d)
         // the last row block may be shorter), or fewer on request.
         int R = (int)std::min<int64_t>(d->tile_rows > 0 ? d->tile_rows : hsk::kMaxTileRows, p->T);
         if (R > hsk::kMaxTileRows ||
-            hsk::fused_lds_bytes((int)p->T, R, p->H, hsk::kModeDetect) > kLdsBudget) {
+            hsk::fused_lds_bytes((int)p->T, R, p->H, hsk::kModeDetect, elem_bytes(p->dtype)) > kLdsBudget) {
             delete p;
             return HS_ERR_UNSUPPORTED;
         }
         p->tile_rows = R;
         p->row_blocks = (int)((p->T + R - 1) / R);
-        p->lds_bytes = hsk::fused_lds_bytes((int)p->T, R, p->H, hsk::kModeDetect);
+        p->lds_bytes = hsk::fused_lds_bytes((int)p->T, R, p->H, hsk::kModeDetect, elem_bytes(p->dtype));
 
         if (d->n_fops == 0) {
             p->tiles_total = p->row_blocks * bin_tiles(p->N);

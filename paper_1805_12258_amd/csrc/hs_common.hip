@@ -22,10 +22,10 @@ __global__ void k_zero_i64(int64_t* p, int64_t n)
         p[e] = 0;
 }
 
-int fused_lds_bytes(int T, int R, int H, int mode)
+int fused_lds_bytes(int T, int R, int H, int mode, int elem_bytes)
 {
     (void)mode;
-    return 2 * stage_words(H) * 4 + smem_tail_bytes(T, R, H);
+    return fused_stage_bytes(H, elem_bytes) + smem_tail_bytes(T, R, H);
 }
 
 #define HS_GROUP_CASES(call)                                                                    \

@@ -38,47 +38,78 @@ struct bf16_t {
 
 template <typename TIn> struct Io;
 
+// Storage access.  one(): a stored value as fp32 (exact).  Prefetched m = 1
+// values stay in registers as raw storage bits (kV fp32 words, or kV halves
+// packed two per word) and are decoded when the tile is summed, so their
+// loads are not waited for at issue: four_raw() loads them, bits() gives one
+// element's storage bits, decode() one value, kNegInf the bits of -inf.
 template <> struct Io<float> {
     using T = float;
+    static constexpr int kWords = kV;
+    static constexpr uint32_t kNegInf = 0xff800000u;
     static __device__ __forceinline__ float one(const T* p) { return *p; }
-    static __device__ __forceinline__ void four(const T* p, float* v)
+    static __device__ __forceinline__ uint32_t bits(const T* p) { return __float_as_uint(*p); }
+    static __device__ __forceinline__ void four_raw(const T* p, uint32_t* r)
     {
-        const float4 x = *reinterpret_cast<const float4*>(p);
-        v[0] = x.x; v[1] = x.y; v[2] = x.z; v[3] = x.w;
+        const uint4 x = *reinterpret_cast<const uint4*>(p);
+        r[0] = x.x; r[1] = x.y; r[2] = x.z; r[3] = x.w;
     }
+    static __device__ __forceinline__ void put(uint32_t* r, int v, uint32_t b) { r[v] = b; }
+    static __device__ __forceinline__ float decode(const uint32_t* r, int v) { return __uint_as_float(r[v]); }
 };
 
 template <> struct Io<_Float16> {
     using T = _Float16;
-    typedef _Float16 h4 __attribute__((ext_vector_type(4)));
+    static constexpr int kWords = kV / 2;
+    static constexpr uint32_t kNegInf = 0xfc00u;
     static __device__ __forceinline__ float one(const T* p) { return (float)*p; }
-    static __device__ __forceinline__ void four(const T* p, float* v)
+    static __device__ __forceinline__ uint32_t bits(const T* p) { return *reinterpret_cast<const uint16_t*>(p); }
+    static __device__ __forceinline__ void four_raw(const T* p, uint32_t* r)
     {
-        const h4 x = *reinterpret_cast<const h4*>(p);
-        v[0] = (float)x.x; v[1] = (float)x.y; v[2] = (float)x.z; v[3] = (float)x.w;
+        const uint2 x = *reinterpret_cast<const uint2*>(p);
+        r[0] = x.x; r[1] = x.y;
+    }
+    static __device__ __forceinline__ void put(uint32_t* r, int v, uint32_t b)
+    {
+        r[v >> 1] = (v & 1) ? (r[v >> 1] | (b << 16)) : b;
+    }
+    static __device__ __forceinline__ float decode(const uint32_t* r, int v)
+    {
+        const uint16_t b = (uint16_t)(r[v >> 1] >> (16 * (v & 1)));
+        _Float16 h;
+        __builtin_memcpy(&h, &b, 2);
+        return (float)h;
     }
 };
 
-// Reduced-precision storage holds power * scale with scale a power of two;
-// converting each stored value to fp32 and multiplying by 1/scale is exact,
-// and power-of-two scaling commutes with every fp32 rounding of the sums, so
-// the planes come out in power units, bitwise equal to the scaled-storage
-// sums divided by scale.
+// Reduced-precision storage holds power * scale with scale a power of two.
+// Sums are formed in storage units; the thresholds are scaled and the
+// reported powers unscaled, both exactly, and power-of-two scaling commutes
+// with every fp32 rounding of the sums, so planes and candidates equal those
+// of the stored values converted to fp32 and divided by scale.
 template <typename TIn> struct Scaled { static constexpr bool value = !std::is_same<TIn, float>::value; };
 
 template <> struct Io<bf16_t> {
     using T = bf16_t;
+    static constexpr int kWords = kV / 2;
+    static constexpr uint32_t kNegInf = 0xff80u;
     static __device__ __forceinline__ float one(const T* p)
     {
         return __uint_as_float((uint32_t)p->bits << 16);
     }
-    static __device__ __forceinline__ void four(const T* p, float* v)
+    static __device__ __forceinline__ uint32_t bits(const T* p) { return p->bits; }
+    static __device__ __forceinline__ void four_raw(const T* p, uint32_t* r)
     {
         const uint2 x = *reinterpret_cast<const uint2*>(p);
-        v[0] = __uint_as_float(x.x << 16);
-        v[1] = __uint_as_float(x.x & 0xffff0000u);
-        v[2] = __uint_as_float(x.y << 16);
-        v[3] = __uint_as_float(x.y & 0xffff0000u);
+        r[0] = x.x; r[1] = x.y;
+    }
+    static __device__ __forceinline__ void put(uint32_t* r, int v, uint32_t b)
+    {
+        r[v >> 1] = (v & 1) ? (r[v >> 1] | (b << 16)) : b;
+    }
+    static __device__ __forceinline__ float decode(const uint32_t* r, int v)
+    {
+        return __uint_as_float((v & 1) ? (r[v >> 1] & 0xffff0000u) : (r[v >> 1] << 16));
     }
 };
 
@@ -98,7 +129,9 @@ __device__ __forceinline__ void static_for(F&& f)
 // covers only one tile) the row table are double-buffered: the loads of the
 // next tile land in one copy while the current tile is summed from the other.
 struct Smem {
-    float* stage[2];              // staged source rows of all m >= 2
+    float* stage[2];              // staged source rows of all m >= 2 (fp32); 16-bit
+                                  // storage uses stage[0] only
+    uint16_t* raw[2];             // 16-bit storage: raw staged halves (DMA targets)
     float* rowtab[2];             // per row: staged-row offsets of m = 2..H, then
                                   // the H thresholds (both entries alias when the
                                   // table covers the whole plane)
@@ -119,13 +152,24 @@ struct FlushParams {
 };
 static_assert(sizeof(FlushParams) <= kFlushParamBytes, "flush parameters");
 
-template <int H>
+template <int H, int EB>
 __device__ __forceinline__ Smem carve(float* lds, int T, int R, bool whole)
 {
     Smem s;
-    s.stage[0] = lds;
-    s.stage[1] = lds + stage_words(H);
-    s.rowtab[0] = lds + 2 * stage_words(H);
+    float* tab;
+    if constexpr (EB == 4) {
+        s.stage[0] = lds;
+        s.stage[1] = lds + stage_words(H);
+        s.raw[0] = s.raw[1] = nullptr;
+        tab = lds + 2 * stage_words(H);
+    } else {
+        constexpr int raw_bytes = (raw_halves(H) * 2 + 15) & ~15;
+        s.stage[0] = s.stage[1] = lds;
+        s.raw[0] = reinterpret_cast<uint16_t*>(lds + stage_words(H));
+        s.raw[1] = reinterpret_cast<uint16_t*>(reinterpret_cast<char*>(s.raw[0]) + raw_bytes);
+        tab = reinterpret_cast<float*>(reinterpret_cast<char*>(s.raw[1]) + raw_bytes);
+    }
+    s.rowtab[0] = tab;
     const int trows = whole ? T : R;
     s.rowtab[1] = whole ? s.rowtab[0] : s.rowtab[0] + trows * row_table_stride(H);
     s.cand = reinterpret_cast<uint64_t*>(s.rowtab[1] + trows * row_table_stride(H));
@@ -219,7 +263,9 @@ __device__ __forceinline__ void emit_hits(const float* acc, float t, int r, int 
             }
             const int pre = (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(mk >> 32),
                                                            __builtin_amdgcn_mbcnt_lo((uint32_t)mk, 0));
-            if (hit) wbuf[ws.n + pre] = ((uint64_t)__float_as_uint(acc[v]) << 32) | (hi | (uint32_t)(jb + v));
+            // sums are in storage units: the reported power is unscaled
+            if (hit)
+                wbuf[ws.n + pre] = ((uint64_t)__float_as_uint(acc[v] * a.inv_scale) << 32) | (hi | (uint32_t)(jb + v));
             ws.n += __builtin_popcountll(mk);
         }
     }
@@ -265,74 +311,118 @@ __device__ __forceinline__ uint32_t src_col_lo(int j0)
 }
 
 // Per-lane byte offsets of this wave's LDS-DMA pieces, relative to the first
-// staged word of the piece's stretch factor (depend on the row pitch ld
-// only, so they are computed once per launch or FOP).  Lanes past the end of
-// a region get 0xffffffff, which every row limit rejects.
-template <int H>
-__device__ __forceinline__ void dma_offsets(int64_t ld, int elem_bytes, uint32_t (&voff)[stage_slot_regs(H)])
+// staged element of the piece's stretch factor (they depend on the row pitch
+// ld only, so they are computed once per launch or FOP): fp32 pieces (EB = 4)
+// of the fp32 staging, or raw pieces (EB = 2) of 16-bit storage.  Lanes past
+// the end of a region get 0xffffffff, which every row limit rejects.
+template <int H, int EB>
+__device__ __forceinline__ void dma_offsets(int64_t ld, uint32_t (&voff)[dma_slot_regs(H, EB)])
 {
     const uint32_t lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const uint32_t ldb = (uint32_t)ld * (uint32_t)elem_bytes;
+    const uint32_t ldb = (uint32_t)ld * (uint32_t)EB;
 #pragma unroll
-    for (int s = 0; s < stage_slots(H); ++s) {
+    for (int s = 0; s < dma_slots(H, EB); ++s) {
         const int g = s * kWaves + wave;
         uint32_t off = 0xffffffffu;
         static_for<2, H>([&](auto mc) {
             constexpr int m = decltype(mc)::value;
-            constexpr int RW = stage_row_words(m);
-            if (g >= stage_chunk_begin(m) && g < stage_chunk_begin(m + 1)) {
-                const uint32_t w = ((uint32_t)(g - stage_chunk_begin(m)) * 64u + lane) * 4u;
-                if (w < (uint32_t)stage_region_words(m)) {
+            constexpr int RW = EB == 4 ? stage_row_words(m) : raw_row_halves(m);
+            constexpr int REG = EB == 4 ? stage_region_words(m) : raw_region_halves(m);
+            constexpr int CB = EB == 4 ? stage_chunk_begin(m) : raw_chunk_begin(m);
+            constexpr int CE = EB == 4 ? stage_chunk_begin(m + 1) : raw_chunk_begin(m + 1);
+            if (g >= CB && g < CE) {
+                const uint32_t w = ((uint32_t)(g - CB) * 64u + lane) * (16u / EB);
+                if (w < (uint32_t)REG) {
                     const uint32_t row = w / RW, col = w - row * RW;
-                    off = row * ldb + col * (uint32_t)elem_bytes;
+                    off = row * ldb + col * (uint32_t)EB;
                 }
             }
         });
         voff[s] = off;
     }
-    if (stage_slots(H) == 0) voff[0] = 0xffffffffu;
+    if (dma_slots(H, EB) == 0) voff[0] = 0xffffffffu;
 }
 
 // LDS-DMA of the pieces of wave W for the tile (r0, j0): piece g = s kWaves + W
 // of region m copies 64 x 16 bytes of source rows src_row_lo<m> + .. into the
-// staging buffer.  Source rows past the plane are masked (row limit); the
-// columns of a full bin tile all lie inside the plane's rows.
-template <int H, int W>
-__device__ __forceinline__ void dma_wave(const TileArgs& a, int r0, int j0, float* stage,
-                                         const uint32_t (&voff)[stage_slot_regs(H)])
+// staging buffer (fp32, EB = 4) or the raw buffer (16-bit, EB = 2, rows
+// starting at floor(j0/m) rounded down to 8 halves).  Source rows past the
+// plane are masked (row limit); the columns of a full bin tile all lie inside
+// the plane's rows.
+template <int H, int W, int EB>
+__device__ __forceinline__ void dma_wave(const TileArgs& a, int r0, int j0, void* dst,
+                                         const uint32_t (&voff)[dma_slot_regs(H, EB)])
 {
-    static_for<0, stage_slots(H) - 1>([&](auto sc) {   // empty for H = 1
+    static_for<0, dma_slots(H, EB) - 1>([&](auto sc) {   // empty for H = 1
         constexpr int s = decltype(sc)::value;
         constexpr int g = s * kWaves + W;
-        if constexpr (g < stage_total_chunks(H)) {
-            constexpr int m = stage_chunk_m(g);
-            constexpr int c = g - stage_chunk_begin(m);
+        constexpr int total = EB == 4 ? stage_total_chunks(H) : raw_total_chunks(H);
+        if constexpr (g < total) {
+            constexpr int m = EB == 4 ? stage_chunk_m(g) : raw_chunk_m(g);
+            constexpr int c = g - (EB == 4 ? stage_chunk_begin(m) : raw_chunk_begin(m));
             const int lo = src_row_lo<m>(r0, a.c);
-            const char* base = reinterpret_cast<const char*>(a.fop) +
-                               ((int64_t)lo * a.ld + src_col_lo<m>(j0)) * 4;
-            const uint64_t lim64 = (uint64_t)(a.T - lo) * (uint64_t)a.ld * 4u;
+            const uint32_t col0 = EB == 4 ? src_col_lo<m>(j0) : (((uint32_t)j0 / (uint32_t)m) & ~7u);
+            const char* base = reinterpret_cast<const char*>(a.fop) + ((int64_t)lo * a.ld + col0) * EB;
+            const uint64_t lim64 = (uint64_t)(a.T - lo) * (uint64_t)a.ld * (uint64_t)EB;
             const uint32_t lim = lim64 > 0xffffffffull ? 0xffffffffu : (uint32_t)lim64;
+            char* d = reinterpret_cast<char*>(dst) +
+                      (EB == 4 ? (stage_offset(m) + c * kDmaWords) * 4 : (raw_offset(m) + c * kDmaHalves) * 2);
             if (voff[s] < lim)
-                __builtin_amdgcn_global_load_lds(reinterpret_cast<const float*>(base + voff[s]),
-                                                 (lds_ptr_t)(stage + stage_offset(m) + c * kDmaWords),
+                __builtin_amdgcn_global_load_lds(reinterpret_cast<const float*>(base + voff[s]), (lds_ptr_t)d,
                                                  16, 0, 0);
         }
     });
 }
 
+// 16-bit storage: the raw staged halves of a tile (all DMA pieces landed)
+// to the fp32 staging layout, four words per thread and step.  The sums stay
+// in storage units (power * scale): the thresholds are scaled to match and
+// the emitted powers are unscaled, all exactly, since scale is a power of
+// two.  Raw reads go through 64-bit integers (LDS accesses with type-based
+// alias information are not ordered after the DMA of the next tile).
+template <typename TIn, int H>
+__device__ __forceinline__ void convert_tile(const uint16_t* raw, float* stage, int j0)
+{
+    static_for<2, H>([&](auto mc) {
+        constexpr int m = decltype(mc)::value;
+        constexpr int RW = stage_row_words(m);
+        constexpr int RH = raw_row_halves(m);
+        const int shift = stage_aligned(m) ? 0 : (int)(((uint32_t)j0 / (uint32_t)m) & 4u);
+        for (int q = threadIdx.x; q < stage_rows(m) * RW / 4; q += kThreads) {
+            const int w = 4 * q;
+            const int row = w / RW, col = w - row * RW;
+            const uint64_t h4 = *reinterpret_cast<const uint64_t*>(raw + raw_offset(m) + row * RH + col + shift);
+            float* o = stage + stage_offset(m) + w;
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const uint16_t bits = (uint16_t)(h4 >> (16 * v));
+                if constexpr (std::is_same<TIn, bf16_t>::value) {
+                    o[v] = __uint_as_float((uint32_t)bits << 16);
+                } else {
+                    _Float16 hv;
+                    __builtin_memcpy(&hv, &bits, 2);
+                    o[v] = (float)hv;
+                }
+            }
+        }
+    });
+}
+
 // Start every load of tile (g.rb, bt): the shrunken source ranges into the
-// staging buffer `stage`, the m = 1 values of the wave's rows into `x`, and
-// (when the row table does not cover the whole plane) the tile's row table
-// into `rowtab`.  Nothing is waited for here.
+// staging buffer `stage` (fp32) or `raw` (16-bit storage, full tiles), the
+// m = 1 values of the wave's rows into `x`, and (when the row table does not
+// cover the whole plane) the tile's row table into `rowtab`.  Nothing is
+// waited for here.  All values stay in storage units (power * scale).
 template <typename TIn, int H, int MODE, bool FULL>
 __device__ __forceinline__ void issue_tile(const TileArgs& a, const RowGeo& g, int bt,
-                                           float* stage, float* rowtab,
-                                           const uint32_t (&voff)[stage_slot_regs(H)],
-                                           float (&x)[kRowsPerWave][kV])
+                                           float* stage, uint16_t* raw, float* rowtab,
+                                           const uint32_t (&voff)[dma_slot_regs(H, sizeof(typename Io<TIn>::T))],
+                                           uint32_t (&x)[kRowsPerWave][kV])
 {
     using Ld = Io<TIn>;
     using T = typename Ld::T;
+    constexpr int EB = sizeof(T);
     const T* __restrict__ fop = reinterpret_cast<const T*>(a.fop);
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -341,19 +431,21 @@ __device__ __forceinline__ void issue_tile(const TileArgs& a, const RowGeo& g, i
     const int j0 = bt * kTileBins;
     const int64_t ld = a.ld;
 
-    // 1. Source ranges.  fp32 full tiles (j0 + kTileBins <= N): LDS-DMA
-    // pieces with precomputed lane offsets.  Otherwise every thread converts
-    // words one at a time (reduced precision is scaled).
-    if constexpr (sizeof(T) == 4 && FULL) {
+    // 1. Source ranges.  Full tiles (j0 + kTileBins <= N): LDS-DMA pieces
+    // with precomputed lane offsets, into the fp32 staging (fp32) or the raw
+    // buffer (16-bit, converted later).  Partial tiles: every thread converts
+    // words one at a time, with bounds checks.
+    if constexpr (FULL) {
+        void* dst = EB == 4 ? static_cast<void*>(stage) : static_cast<void*>(raw);
         switch (wave) {
-        case 0: dma_wave<H, 0>(a, g.r0, j0, stage, voff); break;
-        case 1: dma_wave<H, 1>(a, g.r0, j0, stage, voff); break;
-        case 2: dma_wave<H, 2>(a, g.r0, j0, stage, voff); break;
-        case 3: dma_wave<H, 3>(a, g.r0, j0, stage, voff); break;
-        case 4: dma_wave<H, 4>(a, g.r0, j0, stage, voff); break;
-        case 5: dma_wave<H, 5>(a, g.r0, j0, stage, voff); break;
-        case 6: dma_wave<H, 6>(a, g.r0, j0, stage, voff); break;
-        default: dma_wave<H, 7>(a, g.r0, j0, stage, voff); break;
+        case 0: dma_wave<H, 0, EB>(a, g.r0, j0, dst, voff); break;
+        case 1: dma_wave<H, 1, EB>(a, g.r0, j0, dst, voff); break;
+        case 2: dma_wave<H, 2, EB>(a, g.r0, j0, dst, voff); break;
+        case 3: dma_wave<H, 3, EB>(a, g.r0, j0, dst, voff); break;
+        case 4: dma_wave<H, 4, EB>(a, g.r0, j0, dst, voff); break;
+        case 5: dma_wave<H, 5, EB>(a, g.r0, j0, dst, voff); break;
+        case 6: dma_wave<H, 6, EB>(a, g.r0, j0, dst, voff); break;
+        default: dma_wave<H, 7, EB>(a, g.r0, j0, dst, voff); break;
         }
     } else {
         static_for<2, H>([&](auto mc) {
@@ -364,10 +456,7 @@ __device__ __forceinline__ void issue_tile(const TileArgs& a, const RowGeo& g, i
             for (int e = threadIdx.x; e < stage_region_words(m); e += kThreads) {
                 const int row = e / RW, col = e - row * RW;
                 float v = 0.0f;
-                if (lo + row < a.T && (FULL || cb + col < N)) {
-                    v = Ld::one(fop + (int64_t)(lo + row) * ld + cb + col);
-                    if (Scaled<TIn>::value) v *= a.inv_scale;
-                }
+                if (lo + row < a.T && cb + col < N) v = Ld::one(fop + (int64_t)(lo + row) * ld + cb + col);
                 stage[stage_offset(m) + e] = v;
             }
         });
@@ -382,7 +471,7 @@ __device__ __forceinline__ void issue_tile(const TileArgs& a, const RowGeo& g, i
         for (int q = 0; q < kRowsPerWave; ++q) {
             const int rr = min(wave + kWaves * q, g.nr - 1);
             const T* rowp = fop + (int64_t)(g.r0 + rr) * ld + j0;
-            Ld::four(rowp + kV * lane, x[q]);
+            Ld::four_raw(rowp + kV * lane, x[q]);
         }
     } else {
         const int jb = j0 + kV * lane;
@@ -394,7 +483,7 @@ __device__ __forceinline__ void issue_tile(const TileArgs& a, const RowGeo& g, i
             // threshold (-inf + x is -inf or NaN)
 #pragma unroll
             for (int v = 0; v < kV; ++v)
-                x[q][v] = (rr < g.nr && jb + v < N) ? Ld::one(p + v) : -__builtin_inff();
+                Ld::put(x[q], v, (rr < g.nr && jb + v < N) ? Ld::bits(p + v) : Ld::kNegInf);
         }
     }
 
@@ -419,7 +508,7 @@ __device__ __forceinline__ void issue_tile(const TileArgs& a, const RowGeo& g, i
                 val = __int_as_float(off);
             } else if (MODE == kModeDetect && col >= SO && col < SO + H) {
                 // thresholds exist only in the detection mode (a.ta is null otherwise)
-                val = a.ta[(int64_t)(col - SO) * a.T + r];
+                val = a.ta[(int64_t)(col - SO) * a.T + r] * a.scale;   // storage units (exact)
             }
             rowtab[e] = val;
         }
@@ -432,7 +521,7 @@ template <typename TIn, int H, int MODE, bool FULL>
 __device__ __forceinline__ void compute_tile(const TileArgs& a, const RowGeo& g, int bt,
                                              const Smem& sh, const float* stage,
                                              const float* rowtab,
-                                             const float (&x)[kRowsPerWave][kV], WaveState<H>& ws)
+                                             const uint32_t (&x)[kRowsPerWave][kV], WaveState<H>& ws)
 {
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -492,7 +581,7 @@ __device__ __forceinline__ void compute_tile(const TileArgs& a, const RowGeo& g,
 
         float acc[kV];
 #pragma unroll
-        for (int v = 0; v < kV; ++v) acc[v] = Scaled<TIn>::value ? x[q][v] * a.inv_scale : x[q][v];
+        for (int v = 0; v < kV; ++v) acc[v] = Io<TIn>::decode(x[q], v);
 
         auto emit = [&](int k) {
             if constexpr (MODE == kModeDetect) {
@@ -504,12 +593,15 @@ __device__ __forceinline__ void compute_tile(const TileArgs& a, const RowGeo& g,
                     emit_hits<kV, H>(acc, t, r, k, jb, a, sh, ws, wbuf);
             } else {
                 float* dst = a.hp + ((int64_t)(k - 1) * a.T + r) * N + jb;
+                float o[kV];
+#pragma unroll
+                for (int v = 0; v < kV; ++v) o[v] = Scaled<TIn>::value ? acc[v] * a.inv_scale : acc[v];
                 if (FULL && (N & 3) == 0) {
-                    *reinterpret_cast<float4*>(dst) = make_float4(acc[0], acc[1], acc[2], acc[3]);
+                    *reinterpret_cast<float4*>(dst) = make_float4(o[0], o[1], o[2], o[3]);
                 } else {
 #pragma unroll
                     for (int v = 0; v < kV; ++v)
-                        if (jb + v < N) dst[v] = acc[v];
+                        if (jb + v < N) dst[v] = o[v];
                 }
             }
         };
@@ -540,21 +632,37 @@ __device__ __forceinline__ void compute_tile(const TileArgs& a, const RowGeo& g,
     }
 }
 
+// Meet the other waves after this wave's LDS accesses are done, without
+// waiting for its loads in flight (no release fence, which would wait for
+// every load); the empty asm statements keep the compiler from moving memory
+// accesses across the barrier.
+__device__ __forceinline__ void lds_barrier()
+{
+    __builtin_amdgcn_s_waitcnt(0xc07f);   // lgkmcnt(0); vmcnt and expcnt not waited for
+    asm volatile("" ::: "memory");
+    __builtin_amdgcn_s_barrier();
+    asm volatile("" ::: "memory");
+}
+
 // Tiles [begin, end) of a contiguous run.  Tiles are numbered with the full
 // bin tiles first, row-block-major (t = rb * n_full + bt), then the partial
 // last bin tile of every row block (when N is not a multiple of kTileBins).
 // Full tiles are processed with the loads of tile t+1 in flight while tile t
 // is summed; the two halves of the loop body use the two buffers with static
-// register indices, so no wait on the in-flight loads is implied.  Partial
-// tiles take a plain load-wait-compute loop with bounds checks.
+// register indices, so no wait on the in-flight loads is implied.  16-bit
+// storage converts the landed raw tile into the one fp32 staging buffer
+// first.  Partial tiles take a plain load-wait-compute loop with bounds
+// checks.
 template <typename TIn, int H, int MODE>
 __device__ __forceinline__ void run_tiles(const TileArgs& a, int64_t begin, int64_t end,
-                                          const Smem& sh, const uint32_t (&voff)[stage_slot_regs(H)],
+                                          const Smem& sh,
+                                          const uint32_t (&voff)[dma_slot_regs(H, sizeof(typename Io<TIn>::T))],
                                           WaveState<H>& ws)
 {
+    constexpr bool RAW = sizeof(typename Io<TIn>::T) == 2;
     const int n_full = (int)(a.N / kTileBins);
     const int64_t full_total = (int64_t)a.row_blocks * n_full;
-    float xa[kRowsPerWave][kV], xb[kRowsPerWave][kV];
+    uint32_t xa[kRowsPerWave][kV], xb[kRowsPerWave][kV];   // raw storage bits
     const int64_t fend = end < full_total ? end : full_total;
     if (begin < fend) {
         int rb = (int)(begin / n_full);
@@ -562,36 +670,39 @@ __device__ __forceinline__ void run_tiles(const TileArgs& a, int64_t begin, int6
         RowGeo gc, gn;                    // row geometry of the current / next tile
         row_geo(a, rb, gc);
         gn = gc;
-        __syncthreads();   // the previous run is done with both buffers
-        issue_tile<TIn, H, MODE, true>(a, gc, bt, sh.stage[0], sh.rowtab[0], voff, xa);
+        __syncthreads();   // the previous run is done with every buffer
+        issue_tile<TIn, H, MODE, true>(a, gc, bt, sh.stage[0], sh.raw[0], sh.rowtab[0], voff, xa);
         int64_t t = begin;
-        for (;;) {
+        // one tile from buffer set B (0 or 1), the next tile's loads into 1 - B
+        auto step = [&](auto bc) {
+            constexpr int B = decltype(bc)::value;
+            auto& xc = B == 0 ? xa : xb;
+            auto& xn = B == 0 ? xb : xa;
             int bt1 = bt + 1;
             if (bt1 == n_full) { bt1 = 0; row_geo(a, gc.rb + 1, gn); }
             __builtin_amdgcn_s_waitcnt(0);
             __syncthreads();
-            if (t + 1 < fend) issue_tile<TIn, H, MODE, true>(a, gn, bt1, sh.stage[1], sh.rowtab[1], voff, xb);
-            compute_tile<TIn, H, MODE, true>(a, gc, bt, sh, sh.stage[0], sh.rowtab[0], xa, ws);
+            if (t + 1 < fend)
+                issue_tile<TIn, H, MODE, true>(a, gn, bt1, sh.stage[1 - B], sh.raw[1 - B], sh.rowtab[1 - B], voff, xn);
+            if constexpr (RAW) {
+                convert_tile<TIn, H>(sh.raw[B], sh.stage[0], bt * kTileBins);
+                lds_barrier();
+            }
+            compute_tile<TIn, H, MODE, true>(a, gc, bt, sh, RAW ? sh.stage[0] : sh.stage[B], sh.rowtab[B], xc, ws);
             if (MODE == kModeDetect) maybe_flush<H>(sh, ws);
             gc = gn; bt = bt1;
-            if (++t >= fend) break;
-
-            bt1 = bt + 1;
-            if (bt1 == n_full) { bt1 = 0; row_geo(a, gc.rb + 1, gn); }
-            __builtin_amdgcn_s_waitcnt(0);
-            __syncthreads();
-            if (t + 1 < fend) issue_tile<TIn, H, MODE, true>(a, gn, bt1, sh.stage[0], sh.rowtab[0], voff, xa);
-            compute_tile<TIn, H, MODE, true>(a, gc, bt, sh, sh.stage[1], sh.rowtab[1], xb, ws);
-            if (MODE == kModeDetect) maybe_flush<H>(sh, ws);
-            gc = gn; bt = bt1;
-            if (++t >= fend) break;
+            return ++t < fend;
+        };
+        for (;;) {
+            if (!step(std::integral_constant<int, 0>{})) break;
+            if (!step(std::integral_constant<int, 1>{})) break;
         }
     }
     for (int64_t t = begin > full_total ? begin : full_total; t < end; ++t) {
         RowGeo g;
         row_geo(a, (int)(t - full_total), g);
-        __syncthreads();   // the buffers are free
-        issue_tile<TIn, H, MODE, false>(a, g, n_full, sh.stage[0], sh.rowtab[0], voff, xa);
+        __syncthreads();   // every load in flight has landed; the buffers are free
+        issue_tile<TIn, H, MODE, false>(a, g, n_full, sh.stage[0], sh.raw[0], sh.rowtab[0], voff, xa);
         __builtin_amdgcn_s_waitcnt(0);
         __syncthreads();
         compute_tile<TIn, H, MODE, false>(a, g, n_full, sh, sh.stage[0], sh.rowtab[0], xa, ws);
@@ -602,7 +713,7 @@ __device__ __forceinline__ void run_tiles(const TileArgs& a, int64_t begin, int6
 // Row table for every row of the plane, built once per launch by the whole
 // block: entries of row r refer to the staging layout of r's row block.
 template <int H, int MODE>
-__device__ __forceinline__ void build_whole_table(int T, int R, int c, const float* ta,
+__device__ __forceinline__ void build_whole_table(int T, int R, int c, const float* ta, float scale,
                                                   float* rowtab)
 {
     constexpr int RS = row_table_stride(H);
@@ -620,7 +731,7 @@ __device__ __forceinline__ void build_whole_table(int T, int R, int c, const flo
             });
             val = __int_as_float(off);
         } else if (MODE == kModeDetect && col >= SO && col < SO + H) {
-            val = ta[(int64_t)(col - SO) * T + r];
+            val = ta[(int64_t)(col - SO) * T + r] * scale;   // storage units (exact)
         }
         rowtab[e] = val;
     }
@@ -641,14 +752,15 @@ template <typename TIn, int H, int MODE>
 __global__ __launch_bounds__(kThreads, fused_min_waves<H>()) void k_fused(TileArgs a, int64_t n_tiles)
 {
     extern __shared__ __align__(16) float lds[];
-    const Smem sh = carve<H>(lds, a.T, a.R, a.table_whole != 0);
+    constexpr int EB = sizeof(typename Io<TIn>::T);
+    const Smem sh = carve<H, EB>(lds, a.T, a.R, a.table_whole != 0);
     WaveState<H> ws;
     ws.n = 0;
     if (threadIdx.x < kMaxH) sh.cnt[threadIdx.x] = 0;
-    if (a.table_whole) build_whole_table<H, MODE>(a.T, a.R, a.c, a.ta, sh.rowtab[0]);
+    if (a.table_whole) build_whole_table<H, MODE>(a.T, a.R, a.c, a.ta, a.scale, sh.rowtab[0]);
 
-    uint32_t voff[stage_slot_regs(H)];
-    dma_offsets<H>(a.ld, 4, voff);
+    uint32_t voff[dma_slot_regs(H, EB)];
+    dma_offsets<H, EB>(a.ld, voff);
 
     if (MODE == kModeDetect) set_flush_params(sh, a.out, a.cap, &a.counts[H], a.s_bin, a.kmask);
 
@@ -668,7 +780,8 @@ template <typename TIn, int H>
 __global__ __launch_bounds__(kThreads, fused_min_waves<H>()) void k_batched(BatchArgs b)
 {
     extern __shared__ __align__(16) float lds[];
-    const Smem sh = carve<H>(lds, b.T, b.R, b.table_whole != 0);
+    constexpr int EB = sizeof(typename Io<TIn>::T);
+    const Smem sh = carve<H, EB>(lds, b.T, b.R, b.table_whole != 0);
     WaveState<H> ws;
     ws.n = 0;
     if (threadIdx.x < kMaxH) sh.cnt[threadIdx.x] = 0;
@@ -677,7 +790,7 @@ __global__ __launch_bounds__(kThreads, fused_min_waves<H>()) void k_batched(Batc
     int64_t t0, t1;
     block_chunk(b.tiles_total, t0, t1);
     if (t0 >= t1) return;
-    if (b.table_whole) build_whole_table<H, kModeDetect>(b.T, b.R, b.c, b.ta, sh.rowtab[0]);
+    if (b.table_whole) build_whole_table<H, kModeDetect>(b.T, b.R, b.c, b.ta, b.scale, sh.rowtab[0]);
     // FOP holding tile t0 (binary search over the prefix of tile counts)
     int f;
     {
@@ -716,8 +829,8 @@ __global__ __launch_bounds__(kThreads, fused_min_waves<H>()) void k_batched(Batc
         if (!ok) {
             if (threadIdx.x == 0 && tf == fb) a.counts[H] = ~0ull;
         } else {
-            uint32_t voff[stage_slot_regs(H)];
-            dma_offsets<H>(a.ld, 4, voff);
+            uint32_t voff[dma_slot_regs(H, EB)];
+            dma_offsets<H, EB>(a.ld, voff);
             set_flush_params(sh, a.out, a.cap, &a.counts[H], a.s_bin, a.kmask);
             // tiles of this FOP segment, numbered from the FOP's first tile
             run_tiles<TIn, H, kModeDetect>(a, tf - fb, fe - fb, sh, voff, ws);

@@ -87,6 +87,50 @@ __host__ __device__ constexpr int stage_slots(int H)
 // Registers holding a wave's piece offsets (at least one, for H = 1).
 __host__ __device__ constexpr int stage_slot_regs(int H) { return stage_slots(H) > 0 ? stage_slots(H) : 1; }
 
+// Raw staging of 16-bit FOPs: the same source rectangles as 16-bit halves,
+// loaded by the same 16-byte pieces (8 halves per lane) and converted to the
+// fp32 layout above inside LDS.  A raw row starts at floor(j0/m) rounded down
+// to 8 halves, i.e. (blo & 4) halves before the fp32 row, and holds the fp32
+// row's words after that shift.
+__host__ __device__ constexpr int raw_row_halves(int m)
+{
+    return (stage_row_words(m) + (stage_aligned(m) ? 0 : 4) + 7) & ~7;
+}
+__host__ __device__ constexpr int raw_region_halves(int m) { return stage_rows(m) * raw_row_halves(m); }
+__host__ __device__ constexpr int raw_offset(int m)
+{
+    int o = 0;
+    for (int k = 2; k < m; ++k) o += raw_region_halves(k);
+    return o;
+}
+// Halves of one raw staging buffer for H planes.
+__host__ __device__ constexpr int raw_halves(int H) { return raw_offset(H + 1); }
+constexpr int kDmaHalves = kLanes * 8;
+__host__ __device__ constexpr int raw_chunks(int m) { return (raw_region_halves(m) + kDmaHalves - 1) / kDmaHalves; }
+__host__ __device__ constexpr int raw_chunk_begin(int m)
+{
+    int o = 0;
+    for (int k = 2; k < m; ++k) o += raw_chunks(k);
+    return o;
+}
+__host__ __device__ constexpr int raw_total_chunks(int H) { return raw_chunk_begin(H + 1); }
+__host__ __device__ constexpr int raw_chunk_m(int g)
+{
+    int m = 2;
+    while (g >= raw_chunk_begin(m + 1)) ++m;
+    return m;
+}
+__host__ __device__ constexpr int raw_slots(int H) { return (raw_total_chunks(H) + kWaves - 1) / kWaves; }
+// Piece slots of the storage type: raw pieces for 16-bit storage.
+__host__ __device__ constexpr int dma_slots(int H, int elem_bytes)
+{
+    return elem_bytes == 4 ? stage_slots(H) : raw_slots(H);
+}
+__host__ __device__ constexpr int dma_slot_regs(int H, int elem_bytes)
+{
+    return dma_slots(H, elem_bytes) > 0 ? dma_slots(H, elem_bytes) : 1;
+}
+
 // Row table of a tile: per tile row, the staging offsets of stretch factors
 // 2..H (padded to 4 words) followed by the H thresholds (padded to 4).
 __host__ __device__ constexpr int row_table_thr_offset(int H) { return ((H - 1) + 3) & ~3; }
@@ -169,8 +213,14 @@ struct BatchArgs {
 
 enum Mode { kModeDetect = 0, kModeSum = 1 };
 
-// LDS bytes of the fused kernel for a plan (two staging buffers + tail).
-int fused_lds_bytes(int T, int R, int H, int mode);
+// LDS bytes of the fused kernel: fp32 storage double-buffers the fp32
+// staging; 16-bit storage double-buffers the raw staging and converts into
+// one fp32 staging buffer.
+__host__ __device__ constexpr int fused_stage_bytes(int H, int elem_bytes)
+{
+    return elem_bytes == 4 ? 2 * stage_words(H) * 4 : stage_words(H) * 4 + 2 * ((raw_halves(H) * 2 + 15) & ~15);
+}
+int fused_lds_bytes(int T, int R, int H, int mode, int elem_bytes);
 
 hipError_t launch_fused(int mode, int dtype, int H, const TileArgs& a, int64_t n_tiles,
                         int grid, int lds_bytes, hipStream_t s);
