@@ -160,3 +160,27 @@ def test_large_ragged_h16():
     plan = hs.Plan(T, N, H)
     got = gpu_detect(plan, dev, ta, capacity=1 << 22)
     assert_same_candidates(got, oracle_detect_sorted(store, H, ta, nthreads=16))
+
+
+@pytest.mark.parametrize("name,dtype,u_in,sub", [("f16", torch.float16, 2.0 ** -11, 8 * 2.0 ** -25),
+                                                 ("bf16", torch.bfloat16, 2.0 ** -8, 0.0)])
+def test_reduced_precision_error_bound(name, dtype, u_in, sub):
+    """fp16/bf16 storage of power/8 against the fp64 oracle of the original
+    fp32 plane, at every point of every plane: all terms are >= 0, so
+    |S_gpu - S_64| <= (u_in + (k-1) 2^-24) S_64 + k delta_sub, with u_in the
+    unit roundoff of the storage format and delta_sub the absolute error of
+    an fp16 subnormal (in power units)."""
+    T, N, H = 85, 1 << 16, 8
+    x = synth.noise(T, N, 4000)
+    synth.inject(x, synth.draw_signals(T, N, H, 20, 4000))
+    scale = 0.125
+    store = synth.quantize(x, dtype, scale).cuda()
+    plan = hs.Plan(T, N, H, dtype=name, input_scale=scale)
+    got = plan.sum(store).cpu().numpy().astype(np.float64)
+    ref = oracle.sum_f64(x.numpy(), H)
+    k = np.arange(1, H + 1, dtype=np.float64)[:, None, None]
+    bound = (u_in + (k - 1) * 2.0 ** -24) * ref + k * sub
+    err = np.abs(got - ref)
+    assert np.all(err <= bound * (1 + 1e-12)), float((err / np.maximum(bound, 1e-300)).max())
+    rel = err[ref >= 1.0] / ref[ref >= 1.0]
+    print("%s: max rel error (S >= 1) %.3g, max abs error %.3g" % (name, rel.max(), err.max()))
