@@ -82,6 +82,9 @@ typedef struct hs_plan_desc {
     const int64_t* n_chans;    /* HOST array [n_fops]: bins of each FOP          */
     int32_t tile_rows;         /* tuning: rows per tile, 0 = planner's choice    */
     int32_t persistent_blocks; /* tuning: batched grid size, 0 = planner         */
+    int32_t schedule;          /* tuning, single FOP: 0 = full tiles dealt to    */
+                               /* the eight XCDs so that the sources of m = 2,   */
+                               /* 4, 8 are L2 hits; 1 = contiguous chunks        */
 } hs_plan_desc;
 
 /* Geometry chosen by the planner (host values; no GPU needed). */
@@ -112,6 +115,21 @@ hs_status hs_plan_destroy(hs_plan* plan);
 
 /* Planner geometry, for inspection and tests.  Host only. */
 hs_status hs_plan_info_get(const hs_plan* plan, hs_plan_info* info);
+
+/* The full-tile schedule of a single-FOP plan, for inspection and tests
+ * (host only): words[0..8] are the offsets of eight lists in the entries that
+ * follow, each entry (row_block << 24) | bin_tile; list b % 8 is walked by
+ * block b.  Writes min(capacity, n) words to `words` (host memory, may be
+ * NULL when capacity is 0) and returns n, the schedule's length in words
+ * (0: the plan walks tiles in contiguous chunks), or -1 for a NULL plan. */
+int64_t hs_plan_schedule(const hs_plan* plan, uint32_t* words, int64_t capacity);
+
+/* Single-FOP calls (hs_sum, hs_detect, hs_lse_*): the first such call on a
+ * device that is not under stream capture copies the plan's tile schedule
+ * (4 bytes per full tile, freed by hs_plan_destroy) to that device; before
+ * that copy exists the kernels walk the tiles in contiguous chunks, with
+ * the same results.  Make one eager call before capturing a graph to get the
+ * scheduled order inside the graph. */
 
 /* All harmonic planes (Eq. 1-2), materialised: hp is [n_hp][N_temp][N_chan]
  * fp32 (plane-major, leading dimension N_chan) in unscaled units.

@@ -47,7 +47,8 @@ class hs_plan_desc(ctypes.Structure):
     _fields_ = [("n_temp", ctypes.c_int64), ("n_chan", ctypes.c_int64), ("n_hp", ctypes.c_int32),
                 ("dtype", ctypes.c_int32), ("input_scale", ctypes.c_float),
                 ("n_fops", ctypes.c_int32), ("n_chans", ctypes.POINTER(ctypes.c_int64)),
-                ("tile_rows", ctypes.c_int32), ("persistent_blocks", ctypes.c_int32)]
+                ("tile_rows", ctypes.c_int32), ("persistent_blocks", ctypes.c_int32),
+                ("schedule", ctypes.c_int32)]
 
 
 class hs_plan_info(ctypes.Structure):
@@ -66,6 +67,7 @@ _SIG = {
     "hs_plan_create": ([ctypes.POINTER(_P), ctypes.POINTER(hs_plan_desc)], ctypes.c_int),
     "hs_plan_destroy": ([_P], ctypes.c_int),
     "hs_plan_info_get": ([_P, ctypes.POINTER(hs_plan_info)], ctypes.c_int),
+    "hs_plan_schedule": ([_P, ctypes.POINTER(ctypes.c_uint32), _I64], _I64),
     "hs_sum": ([_P, _P, _I64, _P, _P], ctypes.c_int),
     "hs_detect": ([_P, _P, _I64, _P, _P, _I64, _P, _P], ctypes.c_int),
     "hs_detect_batched": ([_P, _P, _P, _P, _P, _P, _P, _P, _P], ctypes.c_int),
@@ -121,7 +123,7 @@ def _need_cuda(*ts):
 # --- C names --------------------------------------------------------------------
 
 def hs_plan_create(n_temp, n_chan=0, n_hp=8, dtype="f32", input_scale=1.0, n_chans=None,
-                   tile_rows=0, persistent_blocks=0):
+                   tile_rows=0, persistent_blocks=0, schedule=0):
     """Create a plan (host only).  Returns an opaque handle (ctypes.c_void_p)."""
     d = hs_plan_desc()
     d.n_temp = int(n_temp)
@@ -136,6 +138,7 @@ def hs_plan_create(n_temp, n_chan=0, n_hp=8, dtype="f32", input_scale=1.0, n_cha
         d.n_chans = ctypes.cast(keep, ctypes.POINTER(ctypes.c_int64))
     d.tile_rows = int(tile_rows)
     d.persistent_blocks = int(persistent_blocks)
+    d.schedule = int(schedule)
     h = ctypes.c_void_p()
     _check(_c_hs_plan_create(ctypes.byref(h), ctypes.byref(d)), "hs_plan_create")
     return h
@@ -151,6 +154,17 @@ def hs_plan_info_get(handle):
     out = {k: getattr(info, k) for k, _ in hs_plan_info._fields_}
     out["src_rows"] = list(info.src_rows)
     return out
+
+
+def hs_plan_schedule(handle):
+    """The plan's full-tile schedule as a list of uint32 words (host only):
+    nine list offsets, then entries (row_block << 24) | bin_tile."""
+    n = _c_hs_plan_schedule(handle, None, 0)
+    if n < 0:
+        raise HsError(HS_ERR_INVALID, "hs_plan_schedule")
+    buf = (ctypes.c_uint32 * max(n, 1))()
+    _c_hs_plan_schedule(handle, buf, n)
+    return list(buf[:n])
 
 
 def hs_sum(handle, fop, ld, hp, stream=None):
@@ -226,7 +240,7 @@ class Plan:
     """Owning wrapper of an hs_plan handle."""
 
     def __init__(self, n_temp, n_chan=0, n_hp=8, dtype="f32", input_scale=1.0, n_chans=None,
-                 tile_rows=0, persistent_blocks=0):
+                 tile_rows=0, persistent_blocks=0, schedule=0):
         self.n_temp, self.n_hp = int(n_temp), int(n_hp)
         self.n_chan = int(n_chan or 0)
         self.n_chans = None if n_chans is None else [int(x) for x in n_chans]
@@ -237,7 +251,7 @@ class Plan:
         self.torch_dtype = {0: torch.float32, 1: torch.float16, 2: torch.bfloat16}.get(self.dtype)
         self.input_scale = float(input_scale)
         self.handle = hs_plan_create(n_temp, n_chan, n_hp, self.dtype, input_scale, n_chans,
-                                     tile_rows, persistent_blocks)
+                                     tile_rows, persistent_blocks, schedule)
         self.info = hs_plan_info_get(self.handle)
 
     def __del__(self):

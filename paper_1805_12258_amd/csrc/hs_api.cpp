@@ -46,7 +46,75 @@ bool fop_ok(const hs_plan* p, const void* fop, int64_t ld, int64_t N)
     return ld % ld_align(p->dtype) == 0;
 }
 
-hsk::TileArgs tile_args(const hs_plan* p, const void* fop, int64_t ld)
+// Full-tile schedule of a single-FOP plan (the kernel side is described in
+// hs_fused_impl.h).  Bin tile x >= 8 lies in octave L = floor(log2 x); list
+// k holds the tiles whose bits L-1..L-3 equal k (tiles 0..7 go to list x),
+// ordered by their position inside that sub-range scaled to the top octave,
+// then by L (so x/2, x/4, x/8 come just before x), then by row block.
+// Layout: nine list offsets, then the entries (rb << 24) | x.  Empty when
+// the fields do not fit.
+std::vector<uint32_t> build_schedule(int64_t n_full, int row_blocks)
+{
+    std::vector<uint32_t> out;
+    if (n_full < 1 || row_blocks < 1 || row_blocks > 255 || n_full >= ((int64_t)1 << 24)) return out;
+    int top = 0;
+    while (((int64_t)2 << top) <= n_full - 1) ++top;      // floor(log2(n_full - 1)), 0 for n_full <= 2
+    struct E { int64_t key; int L; int64_t x; };
+    std::vector<E> lists[8];
+    for (int64_t x = 0; x < n_full; ++x) {
+        if (x < 8) {
+            lists[x].push_back({0, -1, x});
+            continue;
+        }
+        int L = 3;
+        while (((int64_t)2 << L) <= x) ++L;
+        const int64_t off = x - ((int64_t)1 << L);
+        const int k = (int)(off >> (L - 3));
+        const int64_t pos = off & (((int64_t)1 << (L - 3)) - 1);
+        lists[k].push_back({pos << (top - L), L, x});
+    }
+    out.assign(9, 0);
+    for (int k = 0; k < 8; ++k) {
+        std::sort(lists[k].begin(), lists[k].end(), [](const E& a, const E& b) {
+            if (a.key != b.key) return a.key < b.key;
+            if (a.L != b.L) return a.L < b.L;
+            return a.x < b.x;
+        });
+        out[k + 1] = out[k] + (uint32_t)(lists[k].size() * row_blocks);
+    }
+    for (int k = 0; k < 8; ++k)
+        for (const E& e : lists[k])
+            for (int rb = 0; rb < row_blocks; ++rb) out.push_back(((uint32_t)rb << 24) | (uint32_t)e.x);
+    return out;
+}
+
+// Device copy of the plan's schedule on the current device, made by the
+// first call on that device that is not under stream capture; null when the
+// plan has none or no copy exists yet: the kernels then take contiguous
+// chunks, with the same results.
+const uint32_t* device_sched(const hs_plan* p, hipStream_t stream)
+{
+    if (p->sched.empty()) return nullptr;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return nullptr;
+    std::lock_guard<std::mutex> g(p->mu);
+    if (!p->d_sched[dev]) {
+        hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+        if (hipStreamIsCapturing(stream, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone)
+            return nullptr;
+        uint32_t* d = nullptr;
+        const size_t bytes = p->sched.size() * sizeof(uint32_t);
+        if (hipMalloc(&d, bytes) != hipSuccess) return nullptr;
+        if (hipMemcpy(d, p->sched.data(), bytes, hipMemcpyHostToDevice) != hipSuccess) {
+            (void)hipFree(d);
+            return nullptr;
+        }
+        p->d_sched[dev] = d;
+    }
+    return p->d_sched[dev];
+}
+
+hsk::TileArgs tile_args(const hs_plan* p, const void* fop, int64_t ld, hipStream_t stream)
 {
     hsk::TileArgs a{};
     a.fop = fop;
@@ -62,6 +130,7 @@ hsk::TileArgs tile_args(const hs_plan* p, const void* fop, int64_t ld)
     a.s_bin = p->s_bin;
     a.kmask = (1u << p->s_k) - 1u;
     a.table_whole = hsk::table_whole((int)p->T, p->H) ? 1 : 0;
+    a.sched = device_sched(p, stream);
     return a;
 }
 
@@ -92,6 +161,7 @@ hs_status hs_plan_create(hs_plan** out, const hs_plan_desc* d)
         if (d->dtype == HS_DTYPE_F32 && scale != 1.0f) return HS_ERR_INVALID;
         if (d->n_fops < 0) return HS_ERR_INVALID;
         if (d->tile_rows < 0 || d->persistent_blocks < 0) return HS_ERR_INVALID;
+        if (d->schedule != 0 && d->schedule != 1) return HS_ERR_INVALID;
 
         hs_plan* p = new hs_plan();
         p->T = d->n_temp;
@@ -133,6 +203,7 @@ hs_status hs_plan_create(hs_plan** out, const hs_plan_desc* d)
 
         if (d->n_fops == 0) {
             p->tiles_total = p->row_blocks * bin_tiles(p->N);
+            if (d->schedule == 0) p->sched = build_schedule(p->N / hsk::kTileBins, p->row_blocks);
         } else {
             p->tile_prefix.resize(d->n_fops + 1);
             int64_t acc = 0;
@@ -158,14 +229,23 @@ hs_status hs_plan_destroy(hs_plan* p)
     int cur = -1;
     bool have_dev = hipGetDevice(&cur) == hipSuccess;
     for (int dev = 0; dev < 64; ++dev) {
-        if (p->d_tables[dev]) {
+        if (p->d_tables[dev] || p->d_sched[dev]) {
             if (have_dev) (void)hipSetDevice(dev);
-            (void)hipFree(p->d_tables[dev]);
+            if (p->d_tables[dev]) (void)hipFree(p->d_tables[dev]);
+            if (p->d_sched[dev]) (void)hipFree(p->d_sched[dev]);
         }
     }
     if (have_dev && cur >= 0) (void)hipSetDevice(cur);
     delete p;
     return HS_OK;
+}
+
+int64_t hs_plan_schedule(const hs_plan* p, uint32_t* words, int64_t capacity)
+{
+    if (!p) return -1;
+    const int64_t n = (int64_t)p->sched.size();
+    if (words && capacity > 0) std::memcpy(words, p->sched.data(), (size_t)std::min(n, capacity) * 4);
+    return n;
 }
 
 hs_status hs_plan_info_get(const hs_plan* p, hs_plan_info* info)
@@ -203,7 +283,7 @@ hs_status hs_sum(const hs_plan* p, const void* fop, int64_t ld, float* hp, void*
     if (!p || !hp || p->n_fops != 0) return HS_ERR_INVALID;
     if (!fop_ok(p, fop, ld, p->N)) return HS_ERR_INVALID;
     try {
-        hsk::TileArgs a = tile_args(p, fop, ld);
+        hsk::TileArgs a = tile_args(p, fop, ld, (hipStream_t)stream);
         a.hp = hp;
         return from_hip(hsk::launch_fused(hsk::kModeSum, p->dtype, p->H, a, p->tiles_total,
                                           persistent_grid(p, p->tiles_total), p->lds_bytes,
@@ -223,7 +303,7 @@ hs_status hs_detect(const hs_plan* p, const void* fop, int64_t ld, const float* 
         hipStream_t s = (hipStream_t)stream;
         hipError_t e = hsk::launch_zero_i64(counts, p->H + 1, s);
         if (e != hipSuccess) return HS_ERR_HIP;
-        hsk::TileArgs a = tile_args(p, fop, ld);
+        hsk::TileArgs a = tile_args(p, fop, ld, s);
         a.ta = ta;
         a.out = out;
         a.cap = capacity;
@@ -359,7 +439,7 @@ hs_status hs_lse_forward(const hs_plan* p, const void* fop, int64_t ld, float ta
         hipStream_t s = (hipStream_t)stream;
         float* planes = static_cast<float*>(work);
         void* tail = static_cast<char*>(work) + round256(plane_bytes(p) * p->H);
-        hsk::TileArgs a = tile_args(p, fop, ld);
+        hsk::TileArgs a = tile_args(p, fop, ld, s);
         a.hp = planes;
         hipError_t e = hsk::launch_fused(hsk::kModeSum, p->dtype, p->H, a, p->tiles_total,
                                          persistent_grid(p, p->tiles_total), p->lds_bytes, s);
@@ -379,7 +459,7 @@ hs_status hs_lse_backward(const hs_plan* p, const void* fop, int64_t ld, const d
         hipStream_t s = (hipStream_t)stream;
         float* planes = static_cast<float*>(work);
         float* part = reinterpret_cast<float*>(static_cast<char*>(work) + round256(plane_bytes(p) * p->H));
-        hsk::TileArgs a = tile_args(p, fop, ld);
+        hsk::TileArgs a = tile_args(p, fop, ld, s);
         a.hp = planes;
         hipError_t e = hsk::launch_fused(hsk::kModeSum, p->dtype, p->H, a, p->tiles_total,
                                          persistent_grid(p, p->tiles_total), p->lds_bytes, s);

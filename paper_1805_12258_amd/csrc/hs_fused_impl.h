@@ -13,10 +13,17 @@
 // plane goes to memory in the detection mode.
 //
 // Latency: all loads a wave needs for a tile (its share of the staging and
-// the m = 1 values of all its rows) are issued together at the start of the
-// tile, so a tile costs one memory round trip; several blocks per compute
-// unit overlap one another's round trips.  The grid is persistent: block b
-// walks a contiguous chunk of tiles.
+// the m = 1 values of all its rows) are issued together, one tile ahead of
+// the tile being summed.  The grid is persistent.
+//
+// Reuse: the staged ranges of a tile at bin tile x are the m = 1 data of bin
+// tiles near x/m, read earlier by some other tile.  They come from the L2 of
+// the reading XCD only if the same XCD read them shortly before.  Halving a
+// tile index keeps the bits after its leading one, so the plan deals the bin
+// tiles to the eight XCDs by those three bits and orders each XCD's list by
+// the position inside that sub-range of the octave: x, x/2, x/4 and x/8 then
+// fall on one XCD at nearly the same time, and the ranges of m = 2, 4, 8 are
+// L2 hits.  Without a schedule, block b walks a contiguous chunk of tiles.
 //
 // Candidates: each wave appends its hits to a private LDS buffer (ballot +
 // mbcnt, no atomics) and keeps per-plane counts in scalar registers.  A full
@@ -644,63 +651,99 @@ __device__ __forceinline__ void lds_barrier()
     asm volatile("" ::: "memory");
 }
 
-// Tiles [begin, end) of a contiguous run.  Tiles are numbered with the full
-// bin tiles first, row-block-major (t = rb * n_full + bt), then the partial
-// last bin tile of every row block (when N is not a multiple of kTileBins).
-// Full tiles are processed with the loads of tile t+1 in flight while tile t
-// is summed; the two halves of the loop body use the two buffers with static
-// register indices, so no wait on the in-flight loads is implied.  16-bit
-// storage converts the landed raw tile into the one fp32 staging buffer
-// first.  Partial tiles take a plain load-wait-compute loop with bounds
-// checks.
+// The full bin tiles one block visits: `count` tiles, either entries
+// ids[0], ids[stride], ... of a schedule list ((rb << 24) | bt), or, with
+// ids null, the row-block-major numbers first, first + 1, ... (tile number
+// t = rb * n_full + bt).
+struct TileSeq {
+    const uint32_t* ids;
+    int64_t stride;
+    int64_t first;
+    int64_t count;
+};
+
+__device__ __forceinline__ void seq_tile(const TileSeq& q, int n_full, int64_t k, int& rb, int& bt)
+{
+    if (q.ids) {
+        const uint32_t id = q.ids[k * q.stride];
+        rb = (int)(id >> 24);
+        bt = (int)(id & 0xffffffu);
+    } else {
+        const int64_t t = q.first + k;
+        rb = (int)(t / n_full);
+        bt = (int)(t - (int64_t)rb * n_full);
+    }
+}
+
+// Full tiles of a sequence, processed with the loads of the next tile in
+// flight while the current one is summed; the two halves of the loop body
+// use the two buffers with static register indices, so no wait on the
+// in-flight loads is implied.  16-bit storage converts the landed raw tile
+// into the one fp32 staging buffer first.
 template <typename TIn, int H, int MODE>
-__device__ __forceinline__ void run_tiles(const TileArgs& a, int64_t begin, int64_t end,
-                                          const Smem& sh,
-                                          const uint32_t (&voff)[dma_slot_regs(H, sizeof(typename Io<TIn>::T))],
-                                          WaveState<H>& ws)
+__device__ __forceinline__ void run_full(const TileArgs& a, const TileSeq& q, const Smem& sh,
+                                         const uint32_t (&voff)[dma_slot_regs(H, sizeof(typename Io<TIn>::T))],
+                                         WaveState<H>& ws)
 {
     constexpr bool RAW = sizeof(typename Io<TIn>::T) == 2;
     const int n_full = (int)(a.N / kTileBins);
-    const int64_t full_total = (int64_t)a.row_blocks * n_full;
+    if (q.count <= 0) return;
     uint32_t xa[kRowsPerWave][kV], xb[kRowsPerWave][kV];   // raw storage bits
-    const int64_t fend = end < full_total ? end : full_total;
-    if (begin < fend) {
-        int rb = (int)(begin / n_full);
-        int bt = (int)(begin - (int64_t)rb * n_full);
-        RowGeo gc, gn;                    // row geometry of the current / next tile
-        row_geo(a, rb, gc);
-        gn = gc;
-        __syncthreads();   // the previous run is done with every buffer
-        issue_tile<TIn, H, MODE, true>(a, gc, bt, sh.stage[0], sh.raw[0], sh.rowtab[0], voff, xa);
-        int64_t t = begin;
-        // one tile from buffer set B (0 or 1), the next tile's loads into 1 - B
-        auto step = [&](auto bc) {
-            constexpr int B = decltype(bc)::value;
-            auto& xc = B == 0 ? xa : xb;
-            auto& xn = B == 0 ? xb : xa;
-            int bt1 = bt + 1;
-            if (bt1 == n_full) { bt1 = 0; row_geo(a, gc.rb + 1, gn); }
-            __builtin_amdgcn_s_waitcnt(0);
-            __syncthreads();
-            if (t + 1 < fend)
-                issue_tile<TIn, H, MODE, true>(a, gn, bt1, sh.stage[1 - B], sh.raw[1 - B], sh.rowtab[1 - B], voff, xn);
-            if constexpr (RAW) {
-                convert_tile<TIn, H>(sh.raw[B], sh.stage[0], bt * kTileBins);
-                lds_barrier();
+    int rb, bt;
+    seq_tile(q, n_full, 0, rb, bt);
+    RowGeo gc, gn;                    // row geometry of the current / next tile
+    row_geo(a, rb, gc);
+    gn = gc;
+    __syncthreads();   // the previous run is done with every buffer
+    issue_tile<TIn, H, MODE, true>(a, gc, bt, sh.stage[0], sh.raw[0], sh.rowtab[0], voff, xa);
+    int64_t k = 0;
+    // one tile from buffer set B (0 or 1), the next tile's loads into 1 - B
+    auto step = [&](auto bc) {
+        constexpr int B = decltype(bc)::value;
+        auto& xc = B == 0 ? xa : xb;
+        auto& xn = B == 0 ? xb : xa;
+        const bool more = k + 1 < q.count;
+        int rb1 = gc.rb, bt1 = bt;
+        if (more) {
+            if (q.ids) {
+                seq_tile(q, n_full, k + 1, rb1, bt1);
+            } else if (++bt1 == n_full) {
+                bt1 = 0;
+                ++rb1;
             }
-            compute_tile<TIn, H, MODE, true>(a, gc, bt, sh, RAW ? sh.stage[0] : sh.stage[B], sh.rowtab[B], xc, ws);
-            if (MODE == kModeDetect) maybe_flush<H>(sh, ws);
-            gc = gn; bt = bt1;
-            return ++t < fend;
-        };
-        for (;;) {
-            if (!step(std::integral_constant<int, 0>{})) break;
-            if (!step(std::integral_constant<int, 1>{})) break;
+            if (rb1 != gc.rb) row_geo(a, rb1, gn);
         }
+        __builtin_amdgcn_s_waitcnt(0);
+        __syncthreads();
+        if (more)
+            issue_tile<TIn, H, MODE, true>(a, gn, bt1, sh.stage[1 - B], sh.raw[1 - B], sh.rowtab[1 - B], voff, xn);
+        if constexpr (RAW) {
+            convert_tile<TIn, H>(sh.raw[B], sh.stage[0], bt * kTileBins);
+            lds_barrier();
+        }
+        compute_tile<TIn, H, MODE, true>(a, gc, bt, sh, RAW ? sh.stage[0] : sh.stage[B], sh.rowtab[B], xc, ws);
+        if (MODE == kModeDetect) maybe_flush<H>(sh, ws);
+        gc = gn; bt = bt1;
+        return ++k < q.count;
+    };
+    for (;;) {
+        if (!step(std::integral_constant<int, 0>{})) break;
+        if (!step(std::integral_constant<int, 1>{})) break;
     }
-    for (int64_t t = begin > full_total ? begin : full_total; t < end; ++t) {
+}
+
+// The partial last bin tile of row blocks [begin, end) (N not a multiple of
+// kTileBins): a plain load-wait-compute loop with bounds checks.
+template <typename TIn, int H, int MODE>
+__device__ __forceinline__ void run_partial(const TileArgs& a, int64_t begin, int64_t end, const Smem& sh,
+                                            const uint32_t (&voff)[dma_slot_regs(H, sizeof(typename Io<TIn>::T))],
+                                            WaveState<H>& ws)
+{
+    const int n_full = (int)(a.N / kTileBins);
+    uint32_t xa[kRowsPerWave][kV];
+    for (int64_t t = begin; t < end; ++t) {
         RowGeo g;
-        row_geo(a, (int)(t - full_total), g);
+        row_geo(a, (int)t, g);
         __syncthreads();   // every load in flight has landed; the buffers are free
         issue_tile<TIn, H, MODE, false>(a, g, n_full, sh.stage[0], sh.raw[0], sh.rowtab[0], voff, xa);
         __builtin_amdgcn_s_waitcnt(0);
@@ -708,6 +751,21 @@ __device__ __forceinline__ void run_tiles(const TileArgs& a, int64_t begin, int6
         compute_tile<TIn, H, MODE, false>(a, g, n_full, sh, sh.stage[0], sh.rowtab[0], xa, ws);
         if (MODE == kModeDetect) maybe_flush<H>(sh, ws);
     }
+}
+
+// Tiles [begin, end) of the numbering that puts the full bin tiles first,
+// row-block-major, then the partial last bin tile of every row block.
+template <typename TIn, int H, int MODE>
+__device__ __forceinline__ void run_tiles(const TileArgs& a, int64_t begin, int64_t end, const Smem& sh,
+                                          const uint32_t (&voff)[dma_slot_regs(H, sizeof(typename Io<TIn>::T))],
+                                          WaveState<H>& ws)
+{
+    const int64_t full_total = (int64_t)a.row_blocks * (a.N / kTileBins);
+    const int64_t fend = end < full_total ? end : full_total;
+    const TileSeq q{nullptr, 1, begin, fend - begin};
+    run_full<TIn, H, MODE>(a, q, sh, voff, ws);
+    run_partial<TIn, H, MODE>(a, (begin > full_total ? begin : full_total) - full_total, end - full_total,
+                              sh, voff, ws);
 }
 
 // Row table for every row of the plane, built once per launch by the whole
@@ -764,9 +822,23 @@ __global__ __launch_bounds__(kThreads, fused_min_waves<H>()) void k_fused(TileAr
 
     if (MODE == kModeDetect) set_flush_params(sh, a.out, a.cap, &a.counts[H], a.s_bin, a.kmask);
 
-    int64_t t0, t1;
-    block_chunk(n_tiles, t0, t1);
-    run_tiles<TIn, H, MODE>(a, t0, t1, sh, voff, ws);
+    if (a.sched) {
+        // full tiles from the list of this block's XCD (blocks are dealt to
+        // the eight XCDs in turn), partial tiles in contiguous chunks
+        const int x = blockIdx.x & 7;
+        const int64_t i = blockIdx.x >> 3;
+        const int64_t per = ((int64_t)gridDim.x - x + 7) >> 3;   // blocks on list x
+        const int64_t lo = a.sched[x], len = (int64_t)a.sched[x + 1] - lo;
+        const TileSeq q{a.sched + 9 + lo + i, per, 0, len > i ? (len - i + per - 1) / per : 0};
+        run_full<TIn, H, MODE>(a, q, sh, voff, ws);
+        int64_t p0, p1;
+        block_chunk((a.N % kTileBins) ? a.row_blocks : 0, p0, p1);
+        run_partial<TIn, H, MODE>(a, p0, p1, sh, voff, ws);
+    } else {
+        int64_t t0, t1;
+        block_chunk(n_tiles, t0, t1);
+        run_tiles<TIn, H, MODE>(a, t0, t1, sh, voff, ws);
+    }
 
     if constexpr (MODE == kModeDetect) {
         if (ws.n) flush_wave(sh.cand + (threadIdx.x >> 6) * kWaveCandCap, ws.n, a.out, a.cap,
@@ -822,6 +894,7 @@ __global__ __launch_bounds__(kThreads, fused_min_waves<H>()) void k_batched(Batc
         a.kmask = b.kmask;
         a.table_whole = b.table_whole;
         a.hp = nullptr;
+        a.sched = nullptr;
         constexpr int eb = sizeof(typename Io<TIn>::T);
         const bool ok = ((reinterpret_cast<uintptr_t>(a.fop) & 15) == 0) &&
                         (a.ld % align_elems == 0) && a.ld >= a.N &&
@@ -869,16 +942,20 @@ template <typename TIn, int H>
 static hipError_t launch_fused_t(int mode, const TileArgs& a, int64_t n_tiles, int grid,
                                  int lds_bytes, hipStream_t s)
 {
+    // a schedule needs a block on each of its eight lists
+    TileArgs b = a;
     if (mode == kModeDetect) {
         auto k = k_fused<TIn, H, kModeDetect>;
         (void)hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, lds_bytes);
         const int g = resident_grid(k, lds_bytes, n_tiles, grid);
-        hipLaunchKernelGGL(k, dim3(g), dim3(kThreads), lds_bytes, s, a, n_tiles);
+        if (g < 8) b.sched = nullptr;
+        hipLaunchKernelGGL(k, dim3(g), dim3(kThreads), lds_bytes, s, b, n_tiles);
     } else {
         auto k = k_fused<TIn, H, kModeSum>;
         (void)hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, lds_bytes);
         const int g = resident_grid(k, lds_bytes, n_tiles, grid);
-        hipLaunchKernelGGL(k, dim3(g), dim3(kThreads), lds_bytes, s, a, n_tiles);
+        if (g < 8) b.sched = nullptr;
+        hipLaunchKernelGGL(k, dim3(g), dim3(kThreads), lds_bytes, s, b, n_tiles);
     }
     return hipGetLastError();
 }

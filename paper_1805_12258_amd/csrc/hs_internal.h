@@ -189,6 +189,11 @@ struct TileArgs {
     int32_t table_whole;          // row table covers all T rows (built once)
     // materialised planes
     float* hp;              // [H][T][N]
+    // Full-tile schedule: sched[0..8] are the offsets of eight lists in the
+    // entries that follow, each entry (rb << 24) | bt.  Block b walks list
+    // b % 8 with a stride of the number of blocks that share it.  Null: every
+    // block takes a contiguous chunk of the row-block-major numbering.
+    const uint32_t* sched;
 };
 
 // Arguments of the batched persistent launch.
@@ -259,7 +264,11 @@ struct hs_plan {
     int persistent_blocks = 0;
     std::vector<int64_t> tile_prefix;   // batched: tiles before each FOP
 
-    // Device copies of the batched tables, made on first use per device.
+    std::vector<uint32_t> sched;         // single FOP: full-tile schedule (empty: chunks)
+
+    // Device copies of the batched tables and of the schedule, made at plan
+    // creation on the current device or on first use per device.
     mutable std::mutex mu;
     mutable int64_t* d_tables[64] = {nullptr};
+    mutable uint32_t* d_sched[64] = {nullptr};
 };

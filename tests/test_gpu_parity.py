@@ -64,6 +64,26 @@ def test_row_blocked_tiles(T, N, H, rows):
     assert np.array_equal(hp.view(np.uint32), oracle.sum_f32(store.numpy(), H).view(np.uint32))
 
 
+@pytest.mark.parametrize("T,N,H,blocks", [(85, 256 * 300 + 17, 8, 0), (33, 1 << 16, 16, 13),
+                                           (21, 256 * 40, 8, 100), (85, 256 * 64, 8, 9)])
+def test_schedule_orders(T, N, H, blocks):
+    """The XCD schedule (default) and contiguous chunks give the oracle's
+    planes and candidates, also with grids that leave the eight lists
+    different numbers of blocks."""
+    print("case", T, N, H, blocks, flush=True)
+    x = exp_plane(T, N, 900 + blocks)
+    ta = random_thresholds(H, T, N + blocks)
+    dev, store = padded_device(x)
+    want = oracle_detect_sorted(store, H, ta)
+    ref = oracle.sum_f32(store.numpy(), H)
+    for sched in (0, 1):
+        plan = hs.Plan(T, N, H, persistent_blocks=blocks, schedule=sched)
+        assert (len(hs.hs_plan_schedule(plan.handle)) > 0) == (sched == 0)
+        assert_same_candidates(gpu_detect(plan, dev, ta, capacity=H * T * N), want)
+        hp = plan.sum(dev).cpu().numpy()
+        assert np.array_equal(hp.view(np.uint32), ref.view(np.uint32)), sched
+
+
 def test_every_point_a_candidate():
     """Thresholds of -inf: every point of every plane is a candidate, which
     overflows each block's LDS buffer and exercises the spill path."""

@@ -130,3 +130,36 @@ def test_null_arguments_rejected_without_gpu():
     pb = hs.Plan(21, 0, 8, n_chans=[100, 200])
     assert hs._c_hs_detect(pb.handle, ctypes.c_void_p(0x1000), 1000, out, out, 1, out,
                            null) == hs.HS_ERR_INVALID
+
+
+@pytest.mark.parametrize("T,N", [(85, 1 << 21), (21, 1 << 16), (64, 4097), (85, 3000), (5, 256 * 9),
+                                 (9, 100)])
+def test_tile_schedule(T, N):
+    """The full-tile schedule lists every full tile exactly once; a bin tile
+    and its half (x >> 1, the source tile of m = 2) sit on the same one of
+    the eight lists, the half first; the lists are balanced."""
+    p = hs.Plan(T, N, 8)
+    w = np.array(hs.hs_plan_schedule(p.handle), dtype=np.int64)
+    n_full, nb = N // 256, p.info["row_blocks"]
+    if n_full == 0:
+        assert len(w) == 0
+        return
+    off, ent = w[:9], w[9:]
+    assert off[0] == 0 and off[8] == len(ent) and np.all(np.diff(off) >= 0)
+    rb, bt = ent >> 24, ent & 0xFFFFFF
+    assert np.array_equal(np.sort(rb * n_full + bt), np.arange(nb * n_full))
+    lst = np.searchsorted(off[1:], np.arange(len(ent)), side="right")
+    first = {}
+    for i, (x, r) in enumerate(zip(bt.tolist(), rb.tolist())):
+        if r == 0:
+            first[x] = (lst[i], i)
+    for x in range(16, n_full):
+        assert first[x][0] == first[x >> 1][0], x
+        assert first[x >> 1][1] < first[x][1], x
+    sizes = np.diff(off) // nb
+    assert sizes.max() - sizes.min() <= max(2, n_full // 16)
+    if n_full & (n_full - 1) == 0 and n_full >= 8:
+        assert sizes.min() == sizes.max() == n_full // 8
+    # contiguous chunks on request, and for batched plans
+    assert hs.hs_plan_schedule(hs.Plan(T, N, 8, schedule=1).handle) == []
+    assert hs.hs_plan_schedule(hs.Plan(T, 0, 8, n_chans=[N, N]).handle) == []
