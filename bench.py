@@ -204,6 +204,59 @@ def batched_leg(n_fops, steps, warmup, dev):
             "launch": "one persistent kernel replayed from a captured HIP graph"}
 
 
+def diff_leg(n_fops, steps, warmup, dev):
+    """The differentiation workload: n_fops FOPs of 85 x 2^20 fp32, 8 planes,
+    tau = 0.5.  Forward: lse of every plane (hs_lse_forward); backward: the
+    gradient of L = sum_k tau * lse_k with respect to the FOP
+    (hs_lse_backward, which forms the planes again, turns them into softmax
+    weights and takes them through the transpose).  Timed separately."""
+    import paper_1805_12258_amd as hs
+    import synth
+    cfg = synth.DIFF
+    T, N, H, tau = cfg["n_temp"], cfg["n_chan"], cfg["n_hp"], cfg["tau"]
+    fops = [synth.make_diff_fop(f, device=dev) for f in range(n_fops)]
+    plan = hs.Plan(T, N, H)
+    work = torch.empty(hs.hs_lse_workspace_bytes(plan.handle), dtype=torch.uint8, device=dev)
+    lse = torch.empty((n_fops, H), dtype=torch.float64, device=dev)
+    dfop = torch.empty((T, N), dtype=torch.float32, device=dev)
+
+    def fwd():
+        for f, x in enumerate(fops):
+            hs.hs_lse_forward(plan.handle, x, x.stride(0), tau, lse[f], work)
+
+    def bwd():
+        for f, x in enumerate(fops):
+            hs.hs_lse_backward(plan.handle, x, x.stride(0), lse[f], tau, 1.0, dfop, work)
+
+    out = {}
+    for name, fn in (("forward", fwd), ("backward", bwd)):
+        for _ in range(warmup):
+            fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(steps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        out[name + "_ms"] = e0.elapsed_time(e1) / steps
+    points = n_fops * T * N
+    total = out["forward_ms"] + out["backward_ms"]
+    # per-point bytes of the materialising formulation: forward 4 + 4H
+    # (FOP read, planes written) + 4H (planes read by the reduction);
+    # backward 4 + 4H (planes formed again) + 8H (weights in place) + 4H
+    # (planes read by the transpose) + 4 (gradient written)
+    fb, bb = 4 + 8 * H, 8 + 16 * H
+    out.update({"n_fops": n_fops, "points": points, "value": points / (total * 1e-3),
+                "unit": "points/s (forward + backward)",
+                "forward_gbs": fb * points / (out["forward_ms"] * 1e-3) / 1e9,
+                "backward_gbs": bb * points / (out["backward_ms"] * 1e-3) / 1e9,
+                "bytes_per_point": {"forward": fb, "backward": bb},
+                "loss": float(tau * lse.sum().item())})
+    del fops, work
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -214,6 +267,8 @@ def main():
     ap.add_argument("--cpu-bins", type=int, default=1 << 21)
     ap.add_argument("--batched-fops", type=int, default=512,
                     help="FOPs of the batched leg (0 skips it)")
+    ap.add_argument("--diff-fops", type=int, default=16,
+                    help="FOPs of the differentiation leg (0 skips it)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one plain device copy of the FOP's size (counter scale)")
     args = ap.parse_args()
@@ -303,6 +358,10 @@ def main():
         line["batched"] = batched_leg(args.batched_fops, max(3, args.steps // 40),
                                       2, dev)
         fop = synth.make_ska(device=dev)
+
+    if args.diff_fops > 0:
+        line["differentiation"] = diff_leg(args.diff_fops, 3, 1, dev)
+        torch.cuda.empty_cache()
 
     if not args.no_cpu:
         fop_cpu = fop[:, :args.cpu_bins].cpu()

@@ -4,7 +4,9 @@ Each test names the passage it follows.  None of them compares the oracle with
 a retyped copy of its own loop: they use brute force per point, exact integer
 planes, closed forms, values printed in the paper, or library routines.
 """
+import json
 import math
+import os
 
 import numpy as np
 import pytest
@@ -12,6 +14,15 @@ import pytest
 import oracle
 from oracle import brute
 import synth
+
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
+def golden(name):
+    """A fixture of values printed in the paper (each file cites its passage)."""
+    with open(os.path.join(GOLDEN, name)) as f:
+        return json.load(f)
 
 
 def rand_exp(T, N, seed):
@@ -140,39 +151,45 @@ def test_injected_on_noise_matches_hand_sum():
 
 # --- P6: touch statistics printed in Sec. IV-A ---------------------------------
 
+TOUCH = golden("touch_map_64x4096.json")
+
+
 @pytest.fixture(scope="module")
 def touch64():
-    return oracle.touch_counts(64, 1 << 12, 8, [8])
+    g = TOUCH
+    return oracle.touch_counts(g["n_temp"], g["n_chan"], g["n_hp"], [g["n_hp"]])
 
 
 def test_touch_max_204(touch64):
     """Each point of the deep red area is touched 204 times (= sum m^2)."""
-    assert touch64.max() == 204 == sum(m * m for m in range(1, 9))
-    assert touch64.sum() == 8 * 64 * 4096
+    H = TOUCH["n_hp"]
+    assert touch64.max() == TOUCH["max_touches"] == sum(m * m for m in range(1, H + 1))
+    assert touch64.sum() == H * TOUCH["n_temp"] * TOUCH["n_chan"]
 
 
 def test_touch_zoom_share(touch64):
     """The 16 x 2^10 high-touch area holds 73.4 % of all touches."""
-    c = 32
-    share = touch64[c - 8:c + 8, :1024].sum() / touch64.sum()
-    assert round(share * 100, 1) == 73.4
+    c, h = TOUCH["n_temp"] // 2, TOUCH["zoom_rows"] // 2
+    share = touch64[c - h:c + h, :TOUCH["zoom_bins"]].sum() / touch64.sum()
+    assert round(share * 100, 1) == TOUCH["zoom_share_percent"]
 
 
 def test_touch_deep_red_share(touch64):
     """Points touched 204 times: 1.56 % of the plane (printed as 1.7 %, read
     off a colour map)."""
-    share = (touch64 == 204).mean() * 100
-    assert 1.5 <= share <= 1.7
+    share = (touch64 == TOUCH["max_touches"]).mean() * 100
+    assert TOUCH["deep_red_share_percent"] - 0.2 <= share <= TOUCH["deep_red_share_percent"]
 
 
 def test_touch_cumulative_shares(touch64):
     """2.2 % of the points carry about 50 % of the touches, 25 % carry 90 %."""
+    g = golden("preload_shares.json")
     s = np.sort(touch64.ravel())[::-1]
     cs = np.cumsum(s) / s.sum()
-    f50 = (np.searchsorted(cs, 0.5) + 1) / s.size
+    f50 = (np.searchsorted(cs, g["touch_share_of_first_half_percent"] / 100) + 1) / s.size
     f90 = (np.searchsorted(cs, 0.9) + 1) / s.size
-    assert round(f50 * 100, 1) == 2.2
-    assert 0.23 <= f90 <= 0.26
+    assert round(f50 * 100, 1) == g["points_percent_for_half_of_touches"]
+    assert abs(f90 * 100 - g["points_percent_for_90_percent"]) <= 2
 
 
 def test_touch_equals_transpose_with_unit_cotangent(touch64):
@@ -210,7 +227,7 @@ def test_loaded_points_table_unoptimised():
     (template rows 1..42), column-aligned work groups: the printed table rows
     (3,6,12,23), (2,4,8,15), (2,4,7,13), (2,4,7,13) for 1, 4, 16, 64 columns."""
     rows_i = np.arange(1, 43)
-    printed = {1: (3, 6, 12, 23), 4: (2, 4, 8, 15), 16: (2, 4, 7, 13), 64: (2, 4, 7, 13)}
+    printed = {int(k): tuple(v) for k, v in golden("staging_counts.json")["loaded_points_unoptimised"].items()}
     for ncol, row in printed.items():
         total = sum(needed_rows(rows_i, m) * max_cols(ncol, m, True) for m in range(1, 9))
         got = tuple(math.ceil(total * p / (ncol * 42)) for p in (1, 2, 4, 8))
@@ -221,11 +238,12 @@ def test_average_points_per_column_16():
     """Sixteen columns per work group need 141.4 points per column on average
     (printed 141.5, i.e. 1.66x the 85-row FOP), counting 2*ceil(42/m)+1 rows
     and the worst-case column span of each stretch factor."""
-    ncol = 16
+    g = golden("staging_counts.json")
+    ncol = g["rfop_columns"]
     tot = sum((2 * math.ceil(42 / m) + 1) * max_cols(ncol, m, False) for m in range(1, 9))
     avg = tot / ncol
-    assert abs(avg - 141.5) < 0.1
-    assert round(avg / 85, 2) == 1.66
+    assert abs(avg - g["rfop_avg_points_per_column"]) < 0.1
+    assert round(avg / g["n_temp"], 2) == g["rfop_size_ratio"]
 
 
 # --- P8: detection statistics on pure noise -------------------------------------
@@ -297,11 +315,12 @@ def test_tiny_workload_detects_all_injected_fundamentals():
 def test_packing_paper_formula():
     """CL1 = F*2^24 + H*2^21 + B for 85 templates, 8 planes, 2^21 bins, with the
     plane field holding k-1 (3 bits for 8 planes)."""
-    N, H = 1 << 21, 8
-    assert oracle.field_bits(85, N, H) == (7, 3, 21)
+    g = golden("candidate_word.json")
+    N, H = g["n_chan"], g["n_hp"]
+    assert oracle.field_bits(g["n_temp"], N, H) == (7, 3, 21)
     for (F, k, B) in [(0, 1, 0), (84, 8, 2 ** 21 - 1), (42, 3, 12345), (1, 2, 1)]:
         w = oracle.pack(F, k, B, N, H)
-        assert w == F * 2 ** 24 + (k - 1) * 2 ** 21 + B
+        assert w == F * 2 ** g["shift_template"] + (k - 1) * 2 ** g["shift_plane"] + B
         r, kk, j = oracle.unpack(np.array([w], dtype=np.uint32), N, H)
         assert (r[0], kk[0], j[0]) == (F, k, B)
     assert oracle.pack(84, 8, 2 ** 21 - 1, N, H) == 0x54FFFFFF
