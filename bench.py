@@ -206,7 +206,8 @@ def batched_leg(n_fops, steps, warmup, dev):
 
 def diff_leg(n_fops, steps, warmup, dev):
     """The differentiation workload: n_fops FOPs of 85 x 2^20 fp32, 8 planes,
-    tau = 0.5.  Forward: lse of every plane (hs_lse_forward); backward: the
+    tau = 0.5.  Forward: lse of every plane (hs_lse_forward, fused: no plane
+    is stored); backward: the
     gradient of L = sum_k tau * lse_k with respect to the FOP
     (hs_lse_backward, which forms the planes again, turns them into softmax
     weights and takes them through the transpose).  Timed separately."""
@@ -242,11 +243,10 @@ def diff_leg(n_fops, steps, warmup, dev):
         out[name + "_ms"] = e0.elapsed_time(e1) / steps
     points = n_fops * T * N
     total = out["forward_ms"] + out["backward_ms"]
-    # per-point bytes of the materialising formulation: forward 4 + 4H
-    # (FOP read, planes written) + 4H (planes read by the reduction);
-    # backward 4 + 4H (planes formed again) + 8H (weights in place) + 4H
-    # (planes read by the transpose) + 4 (gradient written)
-    fb, bb = 4 + 8 * H, 8 + 16 * H
+    # per-point bytes: the fused forward reads the FOP once (4); the
+    # backward materialises, 4 + 4H (planes formed again) + 8H (weights in
+    # place) + 4H (planes read by the transpose) + 4 (gradient written)
+    fb, bb = 4, 8 + 16 * H
     out.update({"n_fops": n_fops, "points": points, "value": points / (total * 1e-3),
                 "unit": "points/s (forward + backward)",
                 "forward_gbs": fb * points / (out["forward_ms"] * 1e-3) / 1e9,

@@ -188,11 +188,15 @@ hs_status hs_sum_backward(const hs_plan* plan, const float* g, float* dfop, void
 
 /* Log-sum-exp statistic of each plane of one FOP (tau > 0):
  *   lse[k-1] = log sum_{i,j} exp(HP_k(i,j) / tau)        ([n_hp] fp64, device)
- * formed with a running maximum and a fixed-order two-level reduction
- * (deterministic).  hs_lse_backward overwrites dfop [N_temp][N_chan] fp32
+ * formed with running maxima and a fixed-order reduction (deterministic for
+ * a given device and plan).  For fp32 plans hs_lse_forward is fused: each
+ * lane keeps a (maximum, sum of exponentials) pair per plane over the points
+ * it forms, the pairs are merged per block and then over the blocks in
+ * order, and no plane is stored; other storage types materialise the planes
+ * in `work` first.  hs_lse_backward overwrites dfop [N_temp][N_chan] fp32
  * with gscale times the gradient of L = sum_k tau * lse[k-1] with respect to
  * the FOP (unscaled units): the weights exp(HP_k / tau - lse[k-1]) taken
- * through hs_sum_backward.  Both materialise the planes in `work`, which
+ * through hs_sum_backward; it materialises the planes in `work`.  `work`
  * must hold hs_lse_workspace_bytes(plan) bytes.  Single-FOP plans only. */
 size_t hs_lse_workspace_bytes(const hs_plan* plan);
 hs_status hs_lse_forward(const hs_plan* plan, const void* fop, int64_t ld, float tau, double* lse,

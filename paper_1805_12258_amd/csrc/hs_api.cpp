@@ -422,13 +422,32 @@ hs_status hs_sum_backward(const hs_plan* p, const float* g, float* dfop, void* w
 }
 
 // Workspace of the statistic: the H planes, then the larger of the backward
-// partials and the reduction's per-block pairs.
+// partials and the reduction's per-block pairs; at least the fused forward's
+// per-block pairs.
 size_t hs_lse_workspace_bytes(const hs_plan* p)
 {
     if (!p || p->n_fops != 0) return 0;
     const size_t tail = std::max(partial_bytes(p), (size_t)hsk::lse_part_bytes(p->H));
-    return round256(plane_bytes(p) * p->H) + round256(tail);
+    const size_t fused = (size_t)hsk::kLseMaxBlocks * p->H * 2 * sizeof(float);
+    return std::max(round256(plane_bytes(p) * p->H) + round256(tail), round256(fused));
 }
+
+namespace {
+
+// Grid of the fused statistic: two blocks per compute unit (the planner's
+// LDS budget), at most one per tile and kLseMaxBlocks.
+int lse_grid(const hs_plan* p)
+{
+    int dev = 0, cus = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1)
+        cus = 256;
+    int64_t g = p->persistent_blocks > 0 ? p->persistent_blocks : 2 * (int64_t)cus;
+    g = std::min<int64_t>(g, std::min<int64_t>(p->tiles_total, hsk::kLseMaxBlocks));
+    return (int)std::max<int64_t>(g, 1);
+}
+
+}  // namespace
 
 hs_status hs_lse_forward(const hs_plan* p, const void* fop, int64_t ld, float tau, double* lse,
                          void* work, void* stream)
@@ -437,6 +456,18 @@ hs_status hs_lse_forward(const hs_plan* p, const void* fop, int64_t ld, float ta
     if (!fop_ok(p, fop, ld, p->N)) return HS_ERR_INVALID;
     try {
         hipStream_t s = (hipStream_t)stream;
+        if (p->dtype == HS_DTYPE_F32) {
+            // fused: the planes are formed tile by tile and never stored
+            const int g = lse_grid(p);
+            hsk::TileArgs a = tile_args(p, fop, ld, s);
+            a.lse_part = static_cast<float*>(work);
+            a.lse_c = (float)(1.4426950408889634 / (double)p->scale / (double)tau);
+            hipError_t e = hsk::launch_fused(hsk::kModeLse, p->dtype, p->H, a, p->tiles_total, g,
+                                             p->lds_bytes, s);
+            if (e != hipSuccess) return HS_ERR_HIP;
+            return from_hip(hsk::launch_lse_fused_final(a.lse_part, g, p->H, 1.0 / (double)p->scale,
+                                                        (double)tau, lse, s));
+        }
         float* planes = static_cast<float*>(work);
         void* tail = static_cast<char*>(work) + round256(plane_bytes(p) * p->H);
         hsk::TileArgs a = tile_args(p, fop, ld, s);

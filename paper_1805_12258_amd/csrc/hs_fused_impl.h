@@ -188,8 +188,33 @@ __device__ __forceinline__ Smem carve(float* lds, int T, int R, bool whole)
 // Per-wave detection state (a wave-uniform value).
 template <int H>
 struct WaveState {
-    int n;          // entries in the wave's LDS buffer
+    int n;          // detection: entries in the wave's LDS buffer (wave-uniform)
+    float lm[H];    // log-sum-exp: the lane's running maximum of each plane
+    float ls[H];    //   and the sum of exp2((x - lm) * lse_c) over its values
 };
+
+// Merge two (max, sum) pairs of the log-sum-exp in fp32.  A pair with max
+// -inf holds no value; the shift by the larger max keeps every term <= 1.
+__device__ __forceinline__ void lse_pair_merge(float& M, float& S, float M2, float S2, float c)
+{
+    const float nm = fmaxf(M, M2);
+    const float base = nm == -__builtin_inff() ? 0.0f : nm;
+    S = S * __builtin_amdgcn_exp2f((M - base) * c) + S2 * __builtin_amdgcn_exp2f((M2 - base) * c);
+    M = nm;
+}
+
+// Add the lane's kV values of one plane (storage units) to its pair.
+template <int V>
+__device__ __forceinline__ void lse_add(const float (&x)[V], float& M, float& S, float c)
+{
+    const float nm = fmaxf(fmaxf(fmaxf(x[0], x[1]), fmaxf(x[2], x[3])), M);
+    const float base = nm == -__builtin_inff() ? 0.0f : nm;
+    float t = 0.0f;
+#pragma unroll
+    for (int v = 0; v < V; ++v) t = t + __builtin_amdgcn_exp2f((x[v] - base) * c);
+    S = S * __builtin_amdgcn_exp2f((M - base) * c) + t;
+    M = nm;
+}
 
 __device__ __forceinline__ uint64_t read_first_u64(uint64_t x)
 {
@@ -598,6 +623,11 @@ __device__ __forceinline__ void compute_tile(const TileArgs& a, const RowGeo& g,
                 const float mx = fmaxf(fmaxf(acc[0], acc[1]), fmaxf(acc[2], acc[3]));
                 if (__builtin_expect(__builtin_amdgcn_ballot_w64(mx > t) != 0, 0))
                     emit_hits<kV, H>(acc, t, r, k, jb, a, sh, ws, wbuf);
+            } else if constexpr (MODE == kModeLse) {
+                float xv[kV];
+#pragma unroll
+                for (int v = 0; v < kV; ++v) xv[v] = (FULL || jb + v < N) ? acc[v] : -__builtin_inff();
+                lse_add<kV>(xv, ws.lm[k - 1], ws.ls[k - 1], a.lse_c);
             } else {
                 float* dst = a.hp + ((int64_t)(k - 1) * a.T + r) * N + jb;
                 float o[kV];
@@ -795,6 +825,38 @@ __device__ __forceinline__ void build_whole_table(int T, int R, int c, const flo
     }
 }
 
+// The block's (max, sum) pair of every plane: the 64 lanes of a wave are
+// merged with xor shuffles (both partners of a step compute the same pair,
+// fp32 addition being commutative), the waves in order through LDS (the
+// candidate buffers, unused in this mode); thread k writes plane k.
+template <int H>
+__device__ __forceinline__ void lse_block_pairs(const Smem& sh, WaveState<H>& ws, const TileArgs& a)
+{
+    float* buf = reinterpret_cast<float*>(sh.cand);
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+#pragma unroll
+    for (int k = 0; k < H; ++k) {
+        float M = ws.lm[k], S = ws.ls[k];
+#pragma unroll
+        for (int off = 32; off >= 1; off >>= 1) {
+            const float M2 = __shfl_xor(M, off, 64), S2 = __shfl_xor(S, off, 64);
+            lse_pair_merge(M, S, M2, S2, a.lse_c);
+        }
+        if (lane == 0) {
+            buf[(wave * H + k) * 2] = M;
+            buf[(wave * H + k) * 2 + 1] = S;
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x < H) {
+        const int k = threadIdx.x;
+        float M = buf[k * 2], S = buf[k * 2 + 1];
+        for (int w = 1; w < kWaves; ++w) lse_pair_merge(M, S, buf[(w * H + k) * 2], buf[(w * H + k) * 2 + 1], a.lse_c);
+        a.lse_part[((int64_t)blockIdx.x * H + k) * 2] = M;
+        a.lse_part[((int64_t)blockIdx.x * H + k) * 2 + 1] = S;
+    }
+}
+
 // Tiles [t_begin, t_end) of block b for a grid of g blocks over n tiles.
 __device__ __forceinline__ void block_chunk(int64_t n, int64_t& t_begin, int64_t& t_end)
 {
@@ -814,6 +876,13 @@ __global__ __launch_bounds__(kThreads, fused_min_waves<H>()) void k_fused(TileAr
     const Smem sh = carve<H, EB>(lds, a.T, a.R, a.table_whole != 0);
     WaveState<H> ws;
     ws.n = 0;
+    if constexpr (MODE == kModeLse) {
+#pragma unroll
+        for (int k = 0; k < H; ++k) {
+            ws.lm[k] = -__builtin_inff();
+            ws.ls[k] = 0.0f;
+        }
+    }
     if (threadIdx.x < kMaxH) sh.cnt[threadIdx.x] = 0;
     if (a.table_whole) build_whole_table<H, MODE>(a.T, a.R, a.c, a.ta, a.scale, sh.rowtab[0]);
 
@@ -845,6 +914,7 @@ __global__ __launch_bounds__(kThreads, fused_min_waves<H>()) void k_fused(TileAr
                              &a.counts[H], sh.cnt, a.s_bin, a.kmask);
         flush_counts<H>(sh, a.counts);
     }
+    if constexpr (MODE == kModeLse) lse_block_pairs<H>(sh, ws, a);
 }
 
 // Batched persistent kernel: the grid walks the tiles of every FOP.
@@ -950,12 +1020,21 @@ static hipError_t launch_fused_t(int mode, const TileArgs& a, int64_t n_tiles, i
         const int g = resident_grid(k, lds_bytes, n_tiles, grid);
         if (g < 8) b.sched = nullptr;
         hipLaunchKernelGGL(k, dim3(g), dim3(kThreads), lds_bytes, s, b, n_tiles);
-    } else {
+    } else if (mode == kModeSum) {
         auto k = k_fused<TIn, H, kModeSum>;
         (void)hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, lds_bytes);
         const int g = resident_grid(k, lds_bytes, n_tiles, grid);
         if (g < 8) b.sched = nullptr;
         hipLaunchKernelGGL(k, dim3(g), dim3(kThreads), lds_bytes, s, b, n_tiles);
+    } else if constexpr (std::is_same<TIn, float>::value) {
+        // log-sum-exp: the caller fixes the grid (one partial pair per block)
+        auto k = k_fused<TIn, H, kModeLse>;
+        if (grid < 1 || grid > kLseMaxBlocks || grid > n_tiles) return hipErrorInvalidValue;
+        (void)hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, lds_bytes);
+        if (grid < 8) b.sched = nullptr;
+        hipLaunchKernelGGL(k, dim3(grid), dim3(kThreads), lds_bytes, s, b, n_tiles);
+    } else {
+        return hipErrorInvalidValue;
     }
     return hipGetLastError();
 }

@@ -215,6 +215,25 @@ __global__ void k_lse_final(const double* __restrict__ pm, const float* __restri
     lse[k] = M + log((double)S);
 }
 
+// Fused statistic, level 2: one thread per plane merges the blocks' pairs
+// (max m_b in storage units, sum s_b of exp((x - m_b) * cd)) in block order,
+// in fp64, cd = inv_scale / tau; lse = M * cd + log(S).
+__global__ void k_lse_fused_final(const float* __restrict__ part, int nblk, int H, double cd,
+                                  double* __restrict__ lse)
+{
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= H) return;
+    double M = -__builtin_inf(), S = 0.0;
+    for (int b = 0; b < nblk; ++b) {
+        const double m2 = part[((int64_t)b * H + k) * 2], s2 = part[((int64_t)b * H + k) * 2 + 1];
+        if (s2 == 0.0) continue;
+        if (S == 0.0) { M = m2; S = s2; continue; }
+        if (m2 > M) { S = S * exp((M - m2) * cd) + s2; M = m2; }
+        else S = S + s2 * exp((m2 - M) * cd);
+    }
+    lse[k] = M * cd + log(S);
+}
+
 // Weights of L = sum_k tau * lse_k: dL/dHP_k = exp(HP_k / tau - lse_k), times gscale.
 __global__ __launch_bounds__(256) void k_lse_weights(float* __restrict__ hp, int64_t plane, int H, double inv_tau,
                                                      const double* __restrict__ lse, float gscale)
@@ -270,6 +289,13 @@ hipError_t launch_lse_reduce(const float* hp, int64_t plane, int H, double tau, 
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_lse_final, dim3(1), dim3(64), 0, s, pm, ps, H, kLseBlocks, lse);
+    return hipGetLastError();
+}
+
+hipError_t launch_lse_fused_final(const float* part, int nblk, int H, double inv_scale, double tau,
+                                  double* lse, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_lse_fused_final, dim3(1), dim3(64), 0, s, part, nblk, H, inv_scale / tau, lse);
     return hipGetLastError();
 }
 

@@ -194,6 +194,10 @@ struct TileArgs {
     // b % 8 with a stride of the number of blocks that share it.  Null: every
     // block takes a contiguous chunk of the row-block-major numbering.
     const uint32_t* sched;
+    // fused log-sum-exp: per block and plane the pair (max, sum of
+    // exp2((x - max) * lse_c)) of the block's values x in storage units
+    float* lse_part;        // [gridDim.x][H][2]
+    float lse_c;            // inv_scale * log2(e) / tau
 };
 
 // Arguments of the batched persistent launch.
@@ -216,7 +220,11 @@ struct BatchArgs {
     int32_t table_whole;
 };
 
-enum Mode { kModeDetect = 0, kModeSum = 1 };
+enum Mode { kModeDetect = 0, kModeSum = 1, kModeLse = 2 };
+
+// Fused log-sum-exp: most blocks one launch may use (the partial pairs of
+// the workspace are sized for it).
+constexpr int kLseMaxBlocks = 4096;
 
 // LDS bytes of the fused kernel: fp32 storage double-buffers the fp32
 // staging; 16-bit storage double-buffers the raw staging and converts into
@@ -240,6 +248,8 @@ hipError_t launch_backward(const float* g, float* dfop, float* part, int T, int6
 int64_t lse_part_bytes(int H);
 hipError_t launch_lse_reduce(const float* hp, int64_t plane, int H, double tau, void* work, double* lse,
                              hipStream_t s);
+hipError_t launch_lse_fused_final(const float* part, int nblk, int H, double inv_scale, double tau,
+                                  double* lse, hipStream_t s);
 hipError_t launch_lse_weights(float* hp, int64_t plane, int H, double tau, const double* lse, float gscale,
                               hipStream_t s);
 
