@@ -244,9 +244,11 @@ def diff_leg(n_fops, steps, warmup, dev):
     points = n_fops * T * N
     total = out["forward_ms"] + out["backward_ms"]
     # per-point bytes: the fused forward reads the FOP once (4); the
-    # backward materialises, 4 + 4H (planes formed again) + 8H (weights in
-    # place) + 4H (planes read by the transpose) + 4 (gradient written)
-    fb, bb = 4, 8 + 16 * H
+    # backward reads the FOP (4), writes the H weight planes formed in the
+    # tile kernel (4H), reads them in the transpose (4H) and writes the
+    # gradient (4); the transpose's tile partials (about 0.6 of a plane) are
+    # not counted
+    fb, bb = 4, 8 + 8 * H
     out.update({"n_fops": n_fops, "points": points, "value": points / (total * 1e-3),
                 "unit": "points/s (forward + backward)",
                 "forward_gbs": fb * points / (out["forward_ms"] * 1e-3) / 1e9,

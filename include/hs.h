@@ -196,7 +196,9 @@ hs_status hs_sum_backward(const hs_plan* plan, const float* g, float* dfop, void
  * in `work` first.  hs_lse_backward overwrites dfop [N_temp][N_chan] fp32
  * with gscale times the gradient of L = sum_k tau * lse[k-1] with respect to
  * the FOP (unscaled units): the weights exp(HP_k / tau - lse[k-1]) taken
- * through hs_sum_backward; it materialises the planes in `work`.  `work`
+ * through hs_sum_backward; it materialises the weights in `work` (fp32
+ * plans form them inside the tile kernel; other storage types store the
+ * planes and turn them into weights in a second pass).  `work`
  * must hold hs_lse_workspace_bytes(plan) bytes.  Single-FOP plans only. */
 size_t hs_lse_workspace_bytes(const hs_plan* plan);
 hs_status hs_lse_forward(const hs_plan* plan, const void* fop, int64_t ld, float tau, double* lse,

@@ -492,11 +492,23 @@ hs_status hs_lse_backward(const hs_plan* p, const void* fop, int64_t ld, const d
         float* part = reinterpret_cast<float*>(static_cast<char*>(work) + round256(plane_bytes(p) * p->H));
         hsk::TileArgs a = tile_args(p, fop, ld, s);
         a.hp = planes;
-        hipError_t e = hsk::launch_fused(hsk::kModeSum, p->dtype, p->H, a, p->tiles_total,
-                                         persistent_grid(p, p->tiles_total), p->lds_bytes, s);
-        if (e != hipSuccess) return HS_ERR_HIP;
-        e = hsk::launch_lse_weights(planes, p->T * p->N, p->H, tau, lse, gscale, s);
-        if (e != hipSuccess) return HS_ERR_HIP;
+        hipError_t e;
+        if (p->dtype == HS_DTYPE_F32) {
+            // the weights straight from the tile kernel (the same fp64
+            // difference and expf as the separate pass below)
+            a.lse = lse;
+            a.inv_tau = 1.0 / (double)tau;
+            a.gscale = gscale;
+            e = hsk::launch_fused(hsk::kModeWeights, p->dtype, p->H, a, p->tiles_total,
+                                  persistent_grid(p, p->tiles_total), p->lds_bytes, s);
+            if (e != hipSuccess) return HS_ERR_HIP;
+        } else {
+            e = hsk::launch_fused(hsk::kModeSum, p->dtype, p->H, a, p->tiles_total,
+                                  persistent_grid(p, p->tiles_total), p->lds_bytes, s);
+            if (e != hipSuccess) return HS_ERR_HIP;
+            e = hsk::launch_lse_weights(planes, p->T * p->N, p->H, tau, lse, gscale, s);
+            if (e != hipSuccess) return HS_ERR_HIP;
+        }
         return from_hip(hsk::launch_backward(planes, dfop, part, (int)p->T, p->N, p->H, p->tile_rows, s));
     } catch (...) {
         return HS_ERR_HIP;

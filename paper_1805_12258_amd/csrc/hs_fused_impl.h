@@ -633,6 +633,11 @@ __device__ __forceinline__ void compute_tile(const TileArgs& a, const RowGeo& g,
                 float o[kV];
 #pragma unroll
                 for (int v = 0; v < kV; ++v) o[v] = Scaled<TIn>::value ? acc[v] * a.inv_scale : acc[v];
+                if constexpr (MODE == kModeWeights) {
+                    const double lk = a.lse[k - 1];
+#pragma unroll
+                    for (int v = 0; v < kV; ++v) o[v] = a.gscale * expf((float)((double)o[v] * a.inv_tau - lk));
+                }
                 if (FULL && (N & 3) == 0) {
                     *reinterpret_cast<float4*>(dst) = make_float4(o[0], o[1], o[2], o[3]);
                 } else {
@@ -1026,6 +1031,16 @@ static hipError_t launch_fused_t(int mode, const TileArgs& a, int64_t n_tiles, i
         const int g = resident_grid(k, lds_bytes, n_tiles, grid);
         if (g < 8) b.sched = nullptr;
         hipLaunchKernelGGL(k, dim3(g), dim3(kThreads), lds_bytes, s, b, n_tiles);
+    } else if (mode == kModeWeights) {
+        if constexpr (std::is_same<TIn, float>::value) {
+            auto k = k_fused<TIn, H, kModeWeights>;
+            (void)hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, lds_bytes);
+            const int g = resident_grid(k, lds_bytes, n_tiles, grid);
+            if (g < 8) b.sched = nullptr;
+            hipLaunchKernelGGL(k, dim3(g), dim3(kThreads), lds_bytes, s, b, n_tiles);
+        } else {
+            return hipErrorInvalidValue;
+        }
     } else if constexpr (std::is_same<TIn, float>::value) {
         // log-sum-exp: the caller fixes the grid (one partial pair per block)
         auto k = k_fused<TIn, H, kModeLse>;

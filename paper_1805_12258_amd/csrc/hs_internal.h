@@ -198,6 +198,11 @@ struct TileArgs {
     // exp2((x - max) * lse_c)) of the block's values x in storage units
     float* lse_part;        // [gridDim.x][H][2]
     float lse_c;            // inv_scale * log2(e) / tau
+    // softmax weights of the statistic, written to hp in place of the planes:
+    // gscale * exp(HP_k / tau - lse[k-1])
+    const double* lse;      // [H] device
+    double inv_tau;
+    float gscale;
 };
 
 // Arguments of the batched persistent launch.
@@ -220,7 +225,7 @@ struct BatchArgs {
     int32_t table_whole;
 };
 
-enum Mode { kModeDetect = 0, kModeSum = 1, kModeLse = 2 };
+enum Mode { kModeDetect = 0, kModeSum = 1, kModeLse = 2, kModeWeights = 3 };
 
 // Fused log-sum-exp: most blocks one launch may use (the partial pairs of
 // the workspace are sized for it).

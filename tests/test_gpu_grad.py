@@ -178,3 +178,31 @@ def test_sort_candidates_canonical(T, N, H):
     wi, wp, wc = oracle_detect_sorted(store, H, ta)
     assert np.array_equal(idx, wi)
     assert np.array_equal(pw.view(np.uint32), wp.view(np.uint32))
+
+
+@pytest.mark.parametrize("blocks", [1, 7, 13, 600])
+def test_lse_fused_grids(blocks):
+    """The fused statistic (fp32 plans) at several grid sizes, also below
+    eight blocks (no tile schedule) and with several tiles per block."""
+    T, N, H, tau = 33, 256 * 40 + 5, 8, 0.5
+    x = synth.noise(T, N, 70 + blocks)
+    synth.inject(x, [(0, 300, 25.0, H)])
+    dev, store = padded_device(x)          # NaN padding: a read past the last bin shows
+    plan = hs.Plan(T, N, H, persistent_blocks=blocks)
+    got = plan.lse(dev, tau).cpu().numpy()
+    ref = olse.lse_f64(oracle.sum_f32(store.numpy(), H), tau)
+    assert np.all(np.abs(got - ref) <= lse_tol(T, N, ref)), (got - ref)
+
+
+@pytest.mark.parametrize("name,dtype", [("f16", torch.float16), ("bf16", torch.bfloat16)])
+def test_lse_reduced_precision_storage(name, dtype):
+    """16-bit storage takes the materialising path: lse of the planes of the
+    stored values (unscaled) against the oracle on the same values."""
+    T, N, H, tau, scale = 21, 3000, 8, 0.7, 0.125
+    x = synth.noise(T, N, 44)
+    store = synth.quantize(x, dtype, scale)
+    plan = hs.Plan(T, N, H, dtype=name, input_scale=scale)
+    got = plan.lse(store.cuda(), tau).cpu().numpy()
+    S = oracle.sum_f32(store.to(torch.float32).numpy(), H) / scale
+    ref = olse.lse_f64(S, tau)
+    assert np.all(np.abs(got - ref) <= lse_tol(T, N, ref)), (got - ref)
