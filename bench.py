@@ -269,6 +269,8 @@ def main():
     ap.add_argument("--cpu-bins", type=int, default=1 << 21)
     ap.add_argument("--batched-fops", type=int, default=512,
                     help="FOPs of the batched leg (0 skips it)")
+    ap.add_argument("--singlehp-steps", type=int, default=10,
+                    help="timed steps of the SingleHP baseline (0 skips it)")
     ap.add_argument("--diff-fops", type=int, default=16,
                     help="FOPs of the differentiation leg (0 skips it)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -333,6 +335,33 @@ def main():
         "hbm_gbs": achieved,
         "plane_points_per_s": H * points / (r["ms_per_step"] * 1e-3),
     }
+
+    if args.singlehp_steps > 0:
+        # the paper's SingleHP method (planes through memory) on the same GPU
+        out1 = torch.empty((capacity, 2), dtype=torch.int32, device=dev)
+        cnt1 = torch.empty(H + 1, dtype=torch.int64, device=dev)
+        work1 = torch.empty(hs.hs_singlehp_workspace_bytes(plan.handle), dtype=torch.uint8, device=dev)
+        ld = fop.stride(0)
+        for _ in range(2):
+            hs.hs_detect_singlehp(plan.handle, fop, ld, ta, out1, capacity, cnt1, work1)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(args.singlehp_steps):
+            hs.hs_detect_singlehp(plan.handle, fop, ld, ta, out1, capacity, cnt1, work1)
+        e1.record()
+        torch.cuda.synchronize()
+        sh_ms = e0.elapsed_time(e1) / args.singlehp_steps
+        if not torch.equal(cnt1.cpu(), ref_counts.cpu()):
+            raise RuntimeError("SingleHP and fused candidate counts differ")
+        # bytes per point: FOP read and HP_1 written, then per further plane
+        # HP_{k-1} read, the stretched FOP value, HP_k written
+        sb = 8 + 12 * (H - 1)
+        line["singlehp"] = {"ms_per_step": sh_ms, "value": points / (sh_ms * 1e-3), "unit": "points/s",
+                            "fused_speedup": sh_ms / r["ms_per_step"],
+                            "bytes_per_point": sb, "gbs": sb * points / (sh_ms * 1e-3) / 1e9,
+                            "method": "one launch per plane, each plane written and read back"}
+        del out1, work1
 
     if not args.no_variants:
         var = {}

@@ -148,6 +148,18 @@ hs_status hs_sum(const hs_plan* plan, const void* fop, int64_t ld, float* hp, vo
 hs_status hs_detect(const hs_plan* plan, const void* fop, int64_t ld, const float* ta,
                     hs_cand* out, int64_t capacity, int64_t* counts, void* stream);
 
+/* SingleHP baseline (Sec. IV-B; the kernel of Sec. V-A): the planes are
+ * formed one after another through memory, HP_k = HP_{k-1} + SP_k, one
+ * launch per plane, each plane written to `work` and read back for the next,
+ * and thresholded as it is formed.  Same arguments, results and counts
+ * semantics as hs_detect (the same candidate set, bitwise); it exists to
+ * measure the fused kernel against the paper's baseline method on the same
+ * GPU.  fp32 single-FOP plans only (HS_ERR_UNSUPPORTED otherwise).  `work`:
+ * device memory of hs_singlehp_workspace_bytes(plan) bytes (two planes). */
+size_t hs_singlehp_workspace_bytes(const hs_plan* plan);
+hs_status hs_detect_singlehp(const hs_plan* plan, const float* fop, int64_t ld, const float* ta,
+                             hs_cand* out, int64_t capacity, int64_t* counts, void* work, void* stream);
+
 /* hs_detect over a batch of FOPs of different lengths in one launch of a
  * persistent kernel (no host synchronisation and no allocation inside, so
  * the call can be captured into a HIP graph).  All arrays are DEVICE arrays:

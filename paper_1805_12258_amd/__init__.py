@@ -71,6 +71,8 @@ _SIG = {
     "hs_sum": ([_P, _P, _I64, _P, _P], ctypes.c_int),
     "hs_detect": ([_P, _P, _I64, _P, _P, _I64, _P, _P], ctypes.c_int),
     "hs_detect_batched": ([_P, _P, _P, _P, _P, _P, _P, _P, _P], ctypes.c_int),
+    "hs_singlehp_workspace_bytes": ([_P], ctypes.c_size_t),
+    "hs_detect_singlehp": ([_P, _P, _I64, _P, _P, _I64, _P, _P, _P], ctypes.c_int),
     "hs_sort_workspace_bytes": ([_I64], ctypes.c_size_t),
     "hs_sort_candidates": ([_P, _I64, _P, _P], ctypes.c_int),
     "hs_backward_workspace_bytes": ([_P], ctypes.c_size_t),
@@ -154,6 +156,16 @@ def hs_plan_info_get(handle):
     out = {k: getattr(info, k) for k, _ in hs_plan_info._fields_}
     out["src_rows"] = list(info.src_rows)
     return out
+
+
+def hs_singlehp_workspace_bytes(handle):
+    return int(_c_hs_singlehp_workspace_bytes(handle))
+
+
+def hs_detect_singlehp(handle, fop, ld, ta, out, capacity, counts, work, stream=None):
+    _need_cuda(fop, ta, counts, work)
+    _check(_c_hs_detect_singlehp(handle, _ptr(fop), int(ld), _ptr(ta), _ptr(out), int(capacity),
+                                 _ptr(counts), _ptr(work), _stream(stream)), "hs_detect_singlehp")
 
 
 def hs_plan_schedule(handle):
@@ -291,6 +303,21 @@ class Plan:
         if counts is None:
             counts = torch.empty(self.n_hp + 1, dtype=torch.int64, device=dev)
         hs_detect(self.handle, fop, ld, ta, out, capacity, counts, stream)
+        return out, counts
+
+    def detect_singlehp(self, fop, ta, capacity=None, out=None, counts=None, stream=None):
+        """The SingleHP baseline (plane by plane through memory); same
+        outputs as detect()."""
+        ld = self._fop(fop)
+        dev = fop.device
+        if capacity is None:
+            capacity = out.shape[0] if out is not None else 1 << 20
+        if out is None:
+            out = torch.empty((max(int(capacity), 1), 2), dtype=torch.int32, device=dev)
+        if counts is None:
+            counts = torch.empty(self.n_hp + 1, dtype=torch.int64, device=dev)
+        work = self._work(hs_singlehp_workspace_bytes(self.handle), dev)
+        hs_detect_singlehp(self.handle, fop, ld, ta, out, capacity, counts, work, stream)
         return out, counts
 
     def _work(self, nbytes, device):

@@ -10,6 +10,13 @@
 
 #include "hs_internal.h"
 
+namespace hsk {
+// SingleHP baseline (hs_singlehp.hip)
+hipError_t launch_singlehp(const float* fop, int64_t ld, int T, int N, int H, const float* ta, hs_cand* out,
+                           int64_t cap, unsigned long long* counts, int s_row, int s_bin, float* work,
+                           hipStream_t s);
+}  // namespace hsk
+
 namespace {
 
 int ceil_log2(int64_t x)
@@ -310,6 +317,31 @@ hs_status hs_detect(const hs_plan* p, const void* fop, int64_t ld, const float* 
         a.counts = reinterpret_cast<unsigned long long*>(counts);
         return from_hip(hsk::launch_fused(hsk::kModeDetect, p->dtype, p->H, a, p->tiles_total,
                                           persistent_grid(p, p->tiles_total), p->lds_bytes, s));
+    } catch (...) {
+        return HS_ERR_HIP;
+    }
+}
+
+size_t hs_singlehp_workspace_bytes(const hs_plan* p)
+{
+    if (!p || p->n_fops != 0 || p->dtype != HS_DTYPE_F32) return 0;
+    return 2 * (size_t)((p->T * p->N + 63) & ~(int64_t)63) * sizeof(float);
+}
+
+hs_status hs_detect_singlehp(const hs_plan* p, const float* fop, int64_t ld, const float* ta, hs_cand* out,
+                             int64_t capacity, int64_t* counts, void* work, void* stream)
+{
+    if (!p || p->n_fops != 0 || !ta || !counts || !work || capacity < 0) return HS_ERR_INVALID;
+    if (p->dtype != HS_DTYPE_F32) return HS_ERR_UNSUPPORTED;
+    if (capacity > 0 && !out) return HS_ERR_INVALID;
+    if (!fop_ok(p, fop, ld, p->N)) return HS_ERR_INVALID;
+    try {
+        hipStream_t s = (hipStream_t)stream;
+        hipError_t e = hsk::launch_zero_i64(counts, p->H + 1, s);
+        if (e != hipSuccess) return HS_ERR_HIP;
+        return from_hip(hsk::launch_singlehp(fop, ld, (int)p->T, (int)p->N, p->H, ta, out, capacity,
+                                             reinterpret_cast<unsigned long long*>(counts), p->s_row, p->s_bin,
+                                             static_cast<float*>(work), s));
     } catch (...) {
         return HS_ERR_HIP;
     }

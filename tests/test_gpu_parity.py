@@ -204,3 +204,22 @@ def test_reduced_precision_error_bound(name, dtype, u_in, sub):
     assert np.all(err <= bound * (1 + 1e-12)), float((err / np.maximum(bound, 1e-300)).max())
     rel = err[ref >= 1.0] / ref[ref >= 1.0]
     print("%s: max rel error (S >= 1) %.3g, max abs error %.3g" % (name, rel.max(), err.max()))
+
+
+@pytest.mark.parametrize("T,N,H", [(21, 1000, 8), (64, 4097, 16), (85, 256 * 7 + 3, 8), (1, 300, 3)])
+def test_singlehp_baseline(T, N, H):
+    """The SingleHP baseline (planes through memory) gives the oracle's
+    candidates and counts, bitwise, like the fused kernel."""
+    print("case", T, N, H, flush=True)
+    x = exp_plane(T, N, 500 + T + N)
+    ta = random_thresholds(H, T, N + 3)
+    dev, store = padded_device(x)
+    plan = hs.Plan(T, N, H)
+    cap = H * T * N
+    t = torch.from_numpy(np.ascontiguousarray(ta, dtype=np.float32)).cuda()
+    out, counts = plan.detect_singlehp(dev, t, capacity=cap)
+    counts = counts.cpu().numpy()
+    n = int(counts[-1])
+    a = out[:n].cpu().numpy()
+    got = (a[:, 0].view(np.uint32).copy(), a[:, 1].view(np.float32).copy(), counts)
+    assert_same_candidates(got, oracle_detect_sorted(store, H, ta))
