@@ -336,6 +336,24 @@ def main():
         "plane_points_per_s": H * points / (r["ms_per_step"] * 1e-3),
     }
 
+    # per-plane capped lists (N_cand = 200) from the full candidate list
+    n_all = int(ref_counts[-1].item())
+    sel_out = torch.empty((H, 200, 2), dtype=torch.int32, device=dev)
+    sel_cnt = torch.empty(H, dtype=torch.int64, device=dev)
+    sel_work = torch.empty(max(hs.hs_select_workspace_bytes(plan.handle, n_all), 1), dtype=torch.uint8,
+                           device=dev)
+    hs.hs_select_top(plan.handle, ref_out, n_all, 200, sel_out, sel_cnt, sel_work)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(10):
+        hs.hs_select_top(plan.handle, ref_out, n_all, 200, sel_out, sel_cnt, sel_work)
+    e1.record()
+    torch.cuda.synchronize()
+    line["capped"] = {"n_cand": 200, "candidates_in": n_all, "ms": e0.elapsed_time(e1) / 10,
+                      "kept": int(sel_cnt.sum().item())}
+    del sel_work
+
     if args.singlehp_steps > 0:
         # the paper's SingleHP method (planes through memory) on the same GPU
         out1 = torch.empty((capacity, 2), dtype=torch.int32, device=dev)

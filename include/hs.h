@@ -148,6 +148,21 @@ hs_status hs_sum(const hs_plan* plan, const void* fop, int64_t ld, float* hp, vo
 hs_status hs_detect(const hs_plan* plan, const void* fop, int64_t ld, const float* ta,
                     hs_cand* out, int64_t capacity, int64_t* counts, void* stream);
 
+/* Per-plane capped candidate lists: the N_hp x N_cand list of Sec. III.
+ * Input: a complete candidate list of this plan (cand[0..n), e.g. the first
+ * counts[n_hp] entries of hs_detect when they fit its capacity), not
+ * modified.  Output: out [n_hp][n_cand]; row k-1 holds the n_cand largest
+ * powers of plane k, ties to the smaller CL1 word, in that order (powers
+ * ordered by the IEEE total order of their bits, -0 below +0), and
+ * out_counts [n_hp] int64 (device) the number written to each row,
+ * min(n_cand, candidates of plane k); entries past that are not written.
+ * Deterministic: the same set gives the same lists in any input order.
+ * `work`: device memory of hs_select_workspace_bytes(plan, n) bytes (four
+ * copies of the list plus rocPRIM scratch).  Stream-ordered. */
+size_t hs_select_workspace_bytes(const hs_plan* plan, int64_t n);
+hs_status hs_select_top(const hs_plan* plan, const hs_cand* cand, int64_t n, int32_t n_cand, hs_cand* out,
+                        int64_t* out_counts, void* work, void* stream);
+
 /* SingleHP baseline (Sec. IV-B; the kernel of Sec. V-A): the planes are
  * formed one after another through memory, HP_k = HP_{k-1} + SP_k, one
  * launch per plane, each plane written to `work` and read back for the next,

@@ -180,3 +180,33 @@ def unpack(idx, N, H):
     k = ((idx >> np.uint64(sj)) & np.uint64((1 << sk) - 1)) + np.uint64(1)
     r = idx >> np.uint64(sj + sk)
     return r.astype(np.int64), k.astype(np.int64), j.astype(np.int64)
+
+
+def _power_total_order(pw):
+    """fp32 powers as unsigned keys in the IEEE total order of their bits."""
+    b = np.asarray(pw, dtype=np.float32).view(np.uint32).astype(np.uint64)
+    neg = (b & np.uint64(0x80000000)) != 0
+    return np.where(neg, np.uint64(0xFFFFFFFF) - b, b | np.uint64(0x80000000))
+
+
+def select_top(idx, pw, N, H, n_cand):
+    """Per-plane capped lists (Sec. III: at most N_cand candidates for each
+    of the N_hp planes).  Policy: the n_cand largest powers of plane k
+    (IEEE total order of the fp32 bits), ties to the smaller word, in that
+    order.  Returns (idx [H][n_cand] uint32, pw [H][n_cand] float32,
+    counts [H]); unused slots hold 0."""
+    idx = np.asarray(idx, dtype=np.uint32)
+    pw = np.asarray(pw, dtype=np.float32)
+    _, k, _ = unpack(idx, N, H)
+    key = _power_total_order(pw)
+    out_i = np.zeros((H, n_cand), dtype=np.uint32)
+    out_p = np.zeros((H, n_cand), dtype=np.float32)
+    cnt = np.zeros(H, dtype=np.int64)
+    for kk in range(1, H + 1):
+        sel = np.nonzero(k == kk)[0]
+        # descending power key, then ascending word (lexsort: last key first)
+        order = sel[np.lexsort((idx[sel], -key[sel].astype(np.float64)))][:n_cand]
+        cnt[kk - 1] = len(order)
+        out_i[kk - 1, :len(order)] = idx[order]
+        out_p[kk - 1, :len(order)] = pw[order]
+    return out_i, out_p, cnt

@@ -71,6 +71,8 @@ _SIG = {
     "hs_sum": ([_P, _P, _I64, _P, _P], ctypes.c_int),
     "hs_detect": ([_P, _P, _I64, _P, _P, _I64, _P, _P], ctypes.c_int),
     "hs_detect_batched": ([_P, _P, _P, _P, _P, _P, _P, _P, _P], ctypes.c_int),
+    "hs_select_workspace_bytes": ([_P, _I64], ctypes.c_size_t),
+    "hs_select_top": ([_P, _P, _I64, ctypes.c_int32, _P, _P, _P, _P], ctypes.c_int),
     "hs_singlehp_workspace_bytes": ([_P], ctypes.c_size_t),
     "hs_detect_singlehp": ([_P, _P, _I64, _P, _P, _I64, _P, _P, _P], ctypes.c_int),
     "hs_sort_workspace_bytes": ([_I64], ctypes.c_size_t),
@@ -156,6 +158,16 @@ def hs_plan_info_get(handle):
     out = {k: getattr(info, k) for k, _ in hs_plan_info._fields_}
     out["src_rows"] = list(info.src_rows)
     return out
+
+
+def hs_select_workspace_bytes(handle, n):
+    return int(_c_hs_select_workspace_bytes(handle, int(n)))
+
+
+def hs_select_top(handle, cand, n, n_cand, out, out_counts, work, stream=None):
+    _need_cuda(cand, out, out_counts, work)
+    _check(_c_hs_select_top(handle, _ptr(cand), int(n), int(n_cand), _ptr(out), _ptr(out_counts),
+                            _ptr(work), _stream(stream)), "hs_select_top")
 
 
 def hs_singlehp_workspace_bytes(handle):
@@ -304,6 +316,16 @@ class Plan:
             counts = torch.empty(self.n_hp + 1, dtype=torch.int64, device=dev)
         hs_detect(self.handle, fop, ld, ta, out, capacity, counts, stream)
         return out, counts
+
+    def select_top(self, cand, n, n_cand, stream=None):
+        """Per-plane capped lists from the first n rows of a detect output
+        ([cap][2] int32): returns ([H][n_cand][2] int32, [H] int64)."""
+        dev = cand.device
+        out = torch.zeros((self.n_hp, int(n_cand), 2), dtype=torch.int32, device=dev)
+        cnt = torch.empty(self.n_hp, dtype=torch.int64, device=dev)
+        work = self._work(hs_select_workspace_bytes(self.handle, n), dev)
+        hs_select_top(self.handle, cand, n, n_cand, out, cnt, work, stream)
+        return out, cnt
 
     def detect_singlehp(self, fop, ta, capacity=None, out=None, counts=None, stream=None):
         """The SingleHP baseline (plane by plane through memory); same

@@ -15,6 +15,10 @@ namespace hsk {
 hipError_t launch_singlehp(const float* fop, int64_t ld, int T, int N, int H, const float* ta, hs_cand* out,
                            int64_t cap, unsigned long long* counts, int s_row, int s_bin, float* work,
                            hipStream_t s);
+// Per-plane capped lists (hs_select.hip)
+hipError_t select_workspace(int64_t n, int end_bit, size_t* bytes);
+hipError_t select_top(const uint64_t* cand, int64_t n, int H, int s_bin, int s_k, int n_cand, uint64_t* out,
+                      int64_t* out_counts, void* work, hipStream_t s);
 }  // namespace hsk
 
 namespace {
@@ -317,6 +321,27 @@ hs_status hs_detect(const hs_plan* p, const void* fop, int64_t ld, const float* 
         a.counts = reinterpret_cast<unsigned long long*>(counts);
         return from_hip(hsk::launch_fused(hsk::kModeDetect, p->dtype, p->H, a, p->tiles_total,
                                           persistent_grid(p, p->tiles_total), p->lds_bytes, s));
+    } catch (...) {
+        return HS_ERR_HIP;
+    }
+}
+
+size_t hs_select_workspace_bytes(const hs_plan* p, int64_t n)
+{
+    if (!p || n < 0) return 0;
+    size_t bytes = 0;
+    if (hsk::select_workspace(n, 32 + p->s_k, &bytes) != hipSuccess) return 0;
+    return bytes;
+}
+
+hs_status hs_select_top(const hs_plan* p, const hs_cand* cand, int64_t n, int32_t n_cand, hs_cand* out,
+                        int64_t* out_counts, void* work, void* stream)
+{
+    if (!p || n < 0 || n_cand < 1 || !out || !out_counts || !work) return HS_ERR_INVALID;
+    if (n > 0 && !cand) return HS_ERR_INVALID;
+    try {
+        return from_hip(hsk::select_top(reinterpret_cast<const uint64_t*>(cand), n, p->H, p->s_bin, p->s_k, n_cand,
+                                        reinterpret_cast<uint64_t*>(out), out_counts, work, (hipStream_t)stream));
     } catch (...) {
         return HS_ERR_HIP;
     }

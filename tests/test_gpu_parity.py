@@ -223,3 +223,33 @@ def test_singlehp_baseline(T, N, H):
     a = out[:n].cpu().numpy()
     got = (a[:, 0].view(np.uint32).copy(), a[:, 1].view(np.float32).copy(), counts)
     assert_same_candidates(got, oracle_detect_sorted(store, H, ta))
+
+
+@pytest.mark.parametrize("T,N,H,n_cands", [(21, 1 << 14, 8, (1, 7, 100, 100000)), (33, 3000, 5, (2, 64)),
+                                           (9, 1000, 1, (3,))])
+def test_select_top_capped(T, N, H, n_cands):
+    """Per-plane capped lists from the GPU candidate list equal the oracle's
+    selection from the oracle's list, bitwise, with many exactly tied powers
+    (integer-valued FOP, low thresholds)."""
+    print("case", T, N, H, n_cands, flush=True)
+    rng = np.random.default_rng(T + N + H)
+    x = torch.from_numpy(rng.integers(0, 5, size=(T, N)).astype(np.float32))
+    ta = np.repeat(np.array([k + 1.5 for k in range(1, H + 1)], dtype=np.float32)[:, None], T, axis=1)
+    dev, store = padded_device(x)
+    plan = hs.Plan(T, N, H)
+    out, counts = plan.detect(dev, torch.from_numpy(ta).cuda(), capacity=H * T * N)
+    n = int(counts[-1].item())
+    wi, wp, wc = oracle_detect_sorted(store, H, ta)
+    assert n == len(wi) > 0
+    for n_cand in n_cands:
+        got, cnt = plan.select_top(out, n, n_cand)
+        oi, op, oc = oracle.select_top(wi, wp, N, H, n_cand)
+        assert np.array_equal(cnt.cpu().numpy(), oc), n_cand
+        g = got.cpu().numpy()
+        for k in range(H):
+            c = int(oc[k])
+            assert np.array_equal(g[k, :c, 0].view(np.uint32), oi[k, :c]), (n_cand, k)
+            assert np.array_equal(g[k, :c, 1].view(np.uint32), op[k, :c].view(np.uint32)), (n_cand, k)
+    # an empty list gives zero counts
+    got, cnt = plan.select_top(out, 0, 4)
+    assert np.array_equal(cnt.cpu().numpy(), np.zeros(H, dtype=np.int64))

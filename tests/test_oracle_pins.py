@@ -403,3 +403,35 @@ def test_lse_point_gradient_equals_plane_gradient():
     for a in range(T):
         for b in range(0, N, 7):
             assert lse.grad_point_f64(S, L, tau, a, b, gscale=1.5) == pytest.approx(g[a, b], rel=1e-12)
+
+
+# --- per-plane capped lists (Sec. III: N_cand per plane) --------------------------
+
+def test_select_top_against_sorted_brute_force():
+    """The oracle's capped lists against Python's sorted() with an explicit
+    (plane, -power, word) key on a small list with many tied powers and
+    signed zeros."""
+    rng = np.random.default_rng(3)
+    N, H = 1 << 10, 5
+    n = 400
+    r = rng.integers(0, 7, n)
+    k = rng.integers(1, H + 1, n)
+    j = rng.integers(0, N, n)
+    words = np.array(sorted(set(oracle.pack(a, b, c, N, H) for a, b, c in zip(r, k, j))), dtype=np.uint32)
+    pw = rng.choice(np.array([0.0, -0.0, 1.5, 2.0, 2.0, 7.25, -3.0, 1e30], dtype=np.float32), len(words))
+    perm = rng.permutation(len(words))
+    words, pw = words[perm], pw[perm]
+
+    def total(p):
+        b = int(np.float32(p).view(np.uint32))
+        return (0xFFFFFFFF - b) if b & 0x80000000 else (b | 0x80000000)
+
+    for n_cand in (1, 3, 50, 1000):
+        oi, op, oc = oracle.select_top(words, pw, N, H, n_cand)
+        for kk in range(1, H + 1):
+            mine = [(int(w), p) for w, p in zip(words, pw) if oracle.unpack([w], N, H)[1][0] == kk]
+            want = sorted(mine, key=lambda t: (-total(t[1]), t[0]))[:n_cand]
+            assert oc[kk - 1] == len(want)
+            assert [int(x) for x in oi[kk - 1, :len(want)]] == [w for w, _ in want]
+            got_bits = op[kk - 1, :len(want)].view(np.uint32).tolist()
+            assert got_bits == [int(np.float32(p).view(np.uint32)) for _, p in want]
