@@ -64,6 +64,12 @@ def build(force=True, jobs=None, verbose=True):
                  os.path.getmtime(obj) < max(os.path.getmtime(os.path.join(CSRC, src)), hdr_time))
         if force or stale:
             todo.append((src, obj, flags))
+    # the largest translation units first (more planes unroll to more code)
+    def cost(t):
+        name = t[0]
+        g = int(name.rsplit("_g", 1)[1][0]) if "_fused_" in name else -1
+        return (-g, "f32" not in name)
+    todo.sort(key=cost)
     jobs = jobs or min(8, max(1, os.cpu_count() or 1))
     with cf.ThreadPoolExecutor(jobs) as ex:
         futs = [ex.submit(_compile, *t) for t in todo]

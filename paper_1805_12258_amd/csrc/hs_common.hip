@@ -14,6 +14,13 @@ namespace hsk {
 HS_DECL_TYPE(f32)
 HS_DECL_TYPE(f16)
 HS_DECL_TYPE(bf16)
+#define HS_DECL_STAT(g)                                                                          \
+    hipError_t launch_stat_f32_g##g(int mode, int H, const TileArgs& a, int64_t nt, int grid,     \
+                                    int lds, hipStream_t s);
+HS_DECL_STAT(0)
+HS_DECL_STAT(1)
+HS_DECL_STAT(2)
+HS_DECL_STAT(3)
 
 __global__ void k_zero_i64(int64_t* p, int64_t n)
 {
@@ -41,6 +48,12 @@ hipError_t launch_fused(int mode, int dtype, int H, const TileArgs& a, int64_t n
                         int lds_bytes, hipStream_t s)
 {
     if (H < 1 || H > kMaxH) return hipErrorInvalidValue;
+    if (mode == kModeLse || mode == kModeWeights) {
+        if (dtype != HS_DTYPE_F32) return hipErrorInvalidValue;
+#define HS_CALL(g) launch_stat_f32_g##g(mode, H, a, n_tiles, grid, lds_bytes, s)
+        HS_GROUP_CASES(HS_CALL)
+#undef HS_CALL
+    }
     switch (dtype) {
     case HS_DTYPE_F32: {
 #define HS_CALL(g) launch_fused_f32_g##g(mode, H, a, n_tiles, grid, lds_bytes, s)

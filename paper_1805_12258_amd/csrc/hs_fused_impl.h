@@ -275,24 +275,29 @@ __device__ __forceinline__ void set_flush_params(const Smem& sh, hs_cand* out, i
     }
 }
 
+// Fill at which a wave's buffer is flushed between tiles.
+constexpr int kFlushAt = 64;
+
 // Append the hits of one (row, plane) to the wave's LDS buffer.  Called by
 // the whole wave (uniform control flow): positions come from wave ballots.
-// A buffer without room for 64 more entries is flushed first.
+// A buffer without room for the V * 64 entries one call can add is flushed
+// first (one check per call keeps the inlined copies small).
 template <int V, int H>
 __device__ __forceinline__ void emit_hits(const float* acc, float t, int r, int k, int64_t jb,
                                           const TileArgs& a, const Smem& sh, WaveState<H>& ws,
                                           uint64_t* wbuf)
 {
     const uint32_t hi = (uint32_t)(((uint64_t)r << a.s_row) | ((uint64_t)(k - 1) << a.s_bin));
+    static_assert(kWaveCandCap >= V * 64 + kFlushAt, "candidate buffer");
+    if (__builtin_expect(ws.n > kWaveCandCap - V * 64, 0)) {
+        flush_call(ws.n, wbuf, sh.cnt, sh.fp);
+        ws.n = 0;
+    }
 #pragma unroll
     for (int v = 0; v < V; ++v) {
         const bool hit = acc[v] > t;
         const uint64_t mk = __builtin_amdgcn_ballot_w64(hit);
         if (mk) {
-            if (__builtin_expect(ws.n > kWaveCandCap - 64, 0)) {
-                flush_call(ws.n, wbuf, sh.cnt, sh.fp);
-                ws.n = 0;
-            }
             const int pre = (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(mk >> 32),
                                                            __builtin_amdgcn_mbcnt_lo((uint32_t)mk, 0));
             // sums are in storage units: the reported power is unscaled
@@ -304,7 +309,6 @@ __device__ __forceinline__ void emit_hits(const float* acc, float t, int r, int 
 }
 
 // Flush the wave's buffer once it holds kFlushAt entries (between tiles).
-constexpr int kFlushAt = 64;
 template <int H>
 __device__ __forceinline__ void maybe_flush(const Smem& sh, WaveState<H>& ws)
 {
@@ -1031,19 +1035,27 @@ static hipError_t launch_fused_t(int mode, const TileArgs& a, int64_t n_tiles, i
         const int g = resident_grid(k, lds_bytes, n_tiles, grid);
         if (g < 8) b.sched = nullptr;
         hipLaunchKernelGGL(k, dim3(g), dim3(kThreads), lds_bytes, s, b, n_tiles);
-    } else if (mode == kModeWeights) {
-        if constexpr (std::is_same<TIn, float>::value) {
-            auto k = k_fused<TIn, H, kModeWeights>;
-            (void)hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, lds_bytes);
-            const int g = resident_grid(k, lds_bytes, n_tiles, grid);
-            if (g < 8) b.sched = nullptr;
-            hipLaunchKernelGGL(k, dim3(g), dim3(kThreads), lds_bytes, s, b, n_tiles);
-        } else {
-            return hipErrorInvalidValue;
-        }
-    } else if constexpr (std::is_same<TIn, float>::value) {
-        // log-sum-exp: the caller fixes the grid (one partial pair per block)
-        auto k = k_fused<TIn, H, kModeLse>;
+    } else {
+        return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+// The statistic's modes (fp32 storage only; their own translation units).
+template <int H>
+static hipError_t launch_stat_t(int mode, const TileArgs& a, int64_t n_tiles, int grid, int lds_bytes,
+                                hipStream_t s)
+{
+    TileArgs b = a;
+    if (mode == kModeWeights) {
+        auto k = k_fused<float, H, kModeWeights>;
+        (void)hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, lds_bytes);
+        const int g = resident_grid(k, lds_bytes, n_tiles, grid);
+        if (g < 8) b.sched = nullptr;
+        hipLaunchKernelGGL(k, dim3(g), dim3(kThreads), lds_bytes, s, b, n_tiles);
+    } else if (mode == kModeLse) {
+        // the caller fixes the grid (one partial pair per block)
+        auto k = k_fused<float, H, kModeLse>;
         if (grid < 1 || grid > kLseMaxBlocks || grid > n_tiles) return hipErrorInvalidValue;
         (void)hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, lds_bytes);
         if (grid < 8) b.sched = nullptr;
