@@ -28,17 +28,25 @@ __device__ __forceinline__ uint32_t desc_power_key(uint32_t b)
     return ~asc;
 }
 
+// Sort keys of the second pass and the per-plane counts (counted per block
+// in LDS, then one global atomic per block and plane: a global atomic per
+// entry would serialise on the few counters).
 __global__ __launch_bounds__(kSelThreads) void k_sel_keys(const uint64_t* __restrict__ rec, int64_t n, int s_bin,
                                                           uint32_t kmask, uint64_t* __restrict__ key,
                                                           unsigned long long* __restrict__ cnt)
 {
+    __shared__ unsigned int hist[kMaxH];
+    if (threadIdx.x < kMaxH) hist[threadIdx.x] = 0;
+    __syncthreads();
     for (int64_t i = blockIdx.x * (int64_t)kSelThreads + threadIdx.x; i < n;
          i += (int64_t)gridDim.x * kSelThreads) {
         const uint64_t w = rec[i];
-        const uint32_t k1 = ((uint32_t)w >> s_bin) & kmask;       // plane - 1
+        const uint32_t k1 = ((uint32_t)w >> s_bin) & kmask;       // plane - 1 (kmask < kMaxH)
         key[i] = ((uint64_t)k1 << 32) | desc_power_key((uint32_t)(w >> 32));
-        atomicAdd(&cnt[k1], 1ull);
+        atomicAdd(&hist[k1], 1u);
     }
+    __syncthreads();
+    if (threadIdx.x < kMaxH && hist[threadIdx.x]) atomicAdd(&cnt[threadIdx.x], (unsigned long long)hist[threadIdx.x]);
 }
 
 __global__ __launch_bounds__(kSelThreads) void k_sel_copy(const uint64_t* __restrict__ sorted,
@@ -62,7 +70,7 @@ __global__ __launch_bounds__(kSelThreads) void k_sel_copy(const uint64_t* __rest
 int sel_grid(int64_t n)
 {
     const int64_t b = (n + kSelThreads - 1) / kSelThreads;
-    return (int)(b < 1 ? 1 : (b > 4096 ? 4096 : b));
+    return (int)(b < 1 ? 1 : (b > 1024 ? 1024 : b));
 }
 
 struct SelLayout {
