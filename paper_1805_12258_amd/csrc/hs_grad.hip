@@ -215,23 +215,46 @@ __global__ void k_lse_final(const double* __restrict__ pm, const float* __restri
     lse[k] = M + log((double)S);
 }
 
-// Fused statistic, level 2: one thread per plane merges the blocks' pairs
-// (max m_b in storage units, sum s_b of exp((x - m_b) * cd)) in block order,
-// in fp64, cd = inv_scale / tau; lse = M * cd + log(S).
-__global__ void k_lse_fused_final(const float* __restrict__ part, int nblk, int H, double cd,
-                                  double* __restrict__ lse)
+// Fused statistic, level 2: one block per plane.  The blocks' pairs (max
+// m_b in storage units, sum s_b of exp((x - m_b) * cd)) are merged in fp64,
+// cd = inv_scale / tau: first the largest m_b, then the sum of
+// s_b * exp((m_b - M) * cd); each thread takes a fixed stride of blocks and
+// the threads are combined by a fixed tree (deterministic).
+// lse = M * cd + log(S).
+constexpr int kLseFinalThreads = 256;
+
+__global__ __launch_bounds__(kLseFinalThreads) void k_lse_fused_final(const float* __restrict__ part, int nblk, int H,
+                                                                    double cd, double* __restrict__ lse)
 {
-    const int k = blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= H) return;
-    double M = -__builtin_inf(), S = 0.0;
-    for (int b = 0; b < nblk; ++b) {
-        const double m2 = part[((int64_t)b * H + k) * 2], s2 = part[((int64_t)b * H + k) * 2 + 1];
-        if (s2 == 0.0) continue;
-        if (S == 0.0) { M = m2; S = s2; continue; }
-        if (m2 > M) { S = S * exp((M - m2) * cd) + s2; M = m2; }
-        else S = S + s2 * exp((m2 - M) * cd);
+    const int k = blockIdx.x;
+    __shared__ double red[kLseFinalThreads];
+    double m = -__builtin_inf();
+    for (int b = threadIdx.x; b < nblk; b += kLseFinalThreads) {
+        const double s2 = part[((int64_t)b * H + k) * 2 + 1];
+        if (s2 != 0.0) m = fmax(m, (double)part[((int64_t)b * H + k) * 2]);
     }
-    lse[k] = M * cd + log(S);
+    red[threadIdx.x] = m;
+    __syncthreads();
+    for (int w = kLseFinalThreads / 2; w > 0; w >>= 1) {
+        if (threadIdx.x < w) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + w]);
+        __syncthreads();
+    }
+    const double M = red[0];
+    __syncthreads();
+    double acc = 0.0;
+    if (M != -__builtin_inf()) {
+        for (int b = threadIdx.x; b < nblk; b += kLseFinalThreads) {
+            const double s2 = part[((int64_t)b * H + k) * 2 + 1];
+            if (s2 != 0.0) acc += s2 * exp(((double)part[((int64_t)b * H + k) * 2] - M) * cd);
+        }
+    }
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int w = kLseFinalThreads / 2; w > 0; w >>= 1) {
+        if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) lse[k] = M * cd + log(red[0]);
 }
 
 // Weights of L = sum_k tau * lse_k: dL/dHP_k = exp(HP_k / tau - lse_k), times gscale.
@@ -295,7 +318,7 @@ hipError_t launch_lse_reduce(const float* hp, int64_t plane, int H, double tau, 
 hipError_t launch_lse_fused_final(const float* part, int nblk, int H, double inv_scale, double tau,
                                   double* lse, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_lse_fused_final, dim3(1), dim3(64), 0, s, part, nblk, H, inv_scale / tau, lse);
+    hipLaunchKernelGGL(k_lse_fused_final, dim3(H), dim3(kLseFinalThreads), 0, s, part, nblk, H, inv_scale / tau, lse);
     return hipGetLastError();
 }
 
