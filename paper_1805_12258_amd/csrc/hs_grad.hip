@@ -64,25 +64,43 @@ __global__ __launch_bounds__(kGThreads) void k_bwd_tiles(const float* __restrict
     const int wave = threadIdx.x >> 6;
     const int64_t plane = (int64_t)T * N;
 
-    float s[kGRows][kV];
+    float s[kGRows][kV], nx[kGRows][kV];
 #pragma unroll
     for (int q = 0; q < kGRows; ++q)
 #pragma unroll
         for (int v = 0; v < kV; ++v) s[q][v] = 0.0f;
 
-    for (int m = H; m >= 1; --m) {
-        // suffix sum G_m = g_m + G_{m+1} at the thread's points
+    // g_m at the thread's points, into nx (0 outside the tile); 16-byte
+    // loads when the tile is full and the rows are 16-byte aligned
+    const bool vec = nb == kTileBins && (N & 3) == 0 && (reinterpret_cast<uintptr_t>(g) & 15) == 0;
+    auto load_plane = [&](int m) {
 #pragma unroll
         for (int q = 0; q < kGRows; ++q) {
             const int rr = wave + kGWaves * q;
-            if (rr >= nr) continue;
-            const float* src = g + (int64_t)(m - 1) * plane + (int64_t)(r0 + rr) * N + j0;
+            const float* src = g + (int64_t)(m - 1) * plane + (int64_t)(r0 + (rr < nr ? rr : 0)) * N + j0;
+            if (rr < nr && vec) {
+                const float4 t4 = *reinterpret_cast<const float4*>(src + kV * lane);
+                nx[q][0] = t4.x; nx[q][1] = t4.y; nx[q][2] = t4.z; nx[q][3] = t4.w;
+            } else {
 #pragma unroll
-            for (int v = 0; v < kV; ++v) {
-                const int jj = kV * lane + v;
-                if (jj < nb) s[q][v] = src[jj] + s[q][v];
+                for (int v = 0; v < kV; ++v) {
+                    const int jj = kV * lane + v;
+                    nx[q][v] = (rr < nr && jj < nb) ? src[jj] : 0.0f;
+                }
             }
         }
+    };
+    load_plane(H);
+
+    for (int m = H; m >= 1; --m) {
+        // suffix sum G_m = g_m + G_{m+1} at the thread's points (outside the
+        // tile both are 0)
+#pragma unroll
+        for (int q = 0; q < kGRows; ++q)
+#pragma unroll
+            for (int v = 0; v < kV; ++v) s[q][v] = nx[q][v] + s[q][v];
+        // the next plane's loads fly while this factor's boxes are summed
+        if (m > 1) load_plane(m - 1);
         if (m == 1) {
 #pragma unroll
             for (int q = 0; q < kGRows; ++q) {
