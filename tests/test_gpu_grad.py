@@ -206,3 +206,18 @@ def test_lse_reduced_precision_storage(name, dtype):
     S = oracle.sum_f32(store.to(torch.float32).numpy(), H) / scale
     ref = olse.lse_f64(S, tau)
     assert np.all(np.abs(got - ref) <= lse_tol(T, N, ref)), (got - ref)
+
+
+def test_backward_unaligned_cotangent():
+    """g starting 4 bytes past a 16-byte boundary takes the scalar-load path
+    of the transpose; same bound against the oracle."""
+    T, N, H = 21, 1024, 8
+    rng = np.random.default_rng(12)
+    g = rng.standard_normal((H, T, N)).astype(np.float32)
+    buf = torch.empty(H * T * N + 4, dtype=torch.float32, device="cuda")
+    gv = buf[1:1 + H * T * N].view(H, T, N)
+    gv.copy_(torch.from_numpy(g))
+    assert gv.data_ptr() % 16 == 4
+    got = hs.Plan(T, N, H).backward(gv).cpu().numpy().astype(np.float64)
+    err = np.abs(got - oracle.vjp_f64(g))
+    assert np.all(err <= backward_bound(g, H)), float((err / backward_bound(g, H)).max())
