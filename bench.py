@@ -154,7 +154,13 @@ def batched_leg(n_fops, steps, warmup, dev):
     lds = torch.tensor([x.stride(0) for x in fops], dtype=torch.int64, device=dev)
     offs_d = torch.from_numpy(offs).to(dev)
     caps_d = torch.tensor(caps, dtype=torch.int64, device=dev)
-    plan = hs.Plan(T, 0, H, n_chans=lens)
+    # launch configuration from the autotuner, timed on the first 64 FOPs
+    from paper_1805_12258_amd import autotune
+    t_tune = time.perf_counter()
+    sub = min(64, n_fops)
+    tuned, tuned_ms, _ = autotune.tune(T, 0, H, n_chans=lens[:sub], fops=fops[:sub], ta=ta, reps=3, cache=None)
+    t_tune = time.perf_counter() - t_tune
+    plan = hs.Plan(T, 0, H, n_chans=lens, **tuned)
     args = (plan.handle, fop_ptrs, lds, ta, out, offs_d, caps_d, counts)
     hs.hs_detect_batched(*args)                 # eager call: uploads the plan tables
     torch.cuda.synchronize()
@@ -201,7 +207,8 @@ def batched_leg(n_fops, steps, warmup, dev):
             "ms_per_step": batched_ms, "hbm_gbs": fop_bytes / (batched_ms * 1e-3) / 1e9,
             "per_fop_launches_ms": single_ms, "vs_per_fop": single_ms / batched_ms,
             "candidates": int(batched_counts[:, -1].sum().item()),
-            "launch": "one persistent kernel replayed from a captured HIP graph"}
+            "launch": "one persistent kernel replayed from a captured HIP graph",
+            "autotuned": {"config": tuned, "on_fops": sub, "tuning_s": t_tune}}
 
 
 def diff_leg(n_fops, steps, warmup, dev):

@@ -1,0 +1,166 @@
+"""Autotuner of the plan's launch parameters.
+
+Every candidate configuration computes the same planes and candidate lists
+(the sums do not depend on the tiling or on the order tiles are visited), so
+tuning only changes speed.  Searched: rows per tile (`tile_rows`), the
+persistent grid size (`persistent_blocks`) and, for single-FOP plans, the
+tile order (`schedule`: XCD lists or contiguous chunks).  Bins per tile are
+fixed at compile time (256).
+
+The best configuration per (shape, planes, dtype, FOPs, device) is kept in a
+JSON cache; `tuned_plan` builds a plan from it, tuning first on a miss.
+"""
+import json
+import os
+
+DEFAULT_CACHE = os.path.join(os.path.expanduser("~"), ".cache", "hs_autotune.json")
+
+TILE_ROWS = (0, 24, 16)                 # 0: the planner's choice (32)
+GRID_FACTORS = (0, 1, 3)                # 0: occupancy; else blocks per CU
+SCHEDULES = (0, 1)
+
+
+def candidates(single_fop, cus=256):
+    """The configurations searched (dicts of Plan keyword arguments)."""
+    out = []
+    for r in TILE_ROWS:
+        for f in GRID_FACTORS:
+            for s in (SCHEDULES if single_fop else (0,)):
+                out.append({"tile_rows": r, "persistent_blocks": f * cus, "schedule": s})
+    return out
+
+
+def cache_key(T, N, H, dtype, n_chans, device_name):
+    if n_chans is None:
+        shape = "N%d" % int(N)
+    else:
+        lens = sorted(int(x) for x in n_chans)
+        shape = "F%d:%d-%d:%d" % (len(lens), lens[0], lens[-1], sum(lens))
+    return "%s|T%d|%s|H%d|%s" % (device_name, int(T), shape, int(H), dtype)
+
+
+def load_cache(path):
+    try:
+        with open(path) as f:
+            d = json.load(f)
+        return d if isinstance(d, dict) else {}
+    except (OSError, ValueError):
+        return {}
+
+
+def store_cache(path, key, entry):
+    d = load_cache(path)
+    d[key] = entry
+    os.makedirs(os.path.dirname(os.path.abspath(path)), exist_ok=True)
+    tmp = path + ".tmp%d" % os.getpid()
+    with open(tmp, "w") as f:
+        json.dump(d, f, indent=1, sort_keys=True)
+    os.replace(tmp, path)
+
+
+def search(configs, timer):
+    """The fastest configuration: timer(cfg) returns milliseconds, or None
+    when the configuration is not valid for the shape (skipped).  Ties keep
+    the earlier configuration."""
+    best, best_ms, tried = None, None, []
+    for cfg in configs:
+        ms = timer(cfg)
+        tried.append({"config": cfg, "ms": ms})
+        if ms is not None and (best_ms is None or ms < best_ms):
+            best, best_ms = cfg, ms
+    if best is None:
+        raise RuntimeError("no valid configuration")
+    return best, best_ms, tried
+
+
+def tune(T, N, H, dtype="f32", input_scale=1.0, n_chans=None, fops=None, ta=None, reps=5,
+         cache=DEFAULT_CACHE, cus=None):
+    """Time every candidate configuration on device-resident input and
+    return (best config, best ms, all timings); the best is stored in
+    `cache` (None: not stored).  `fops` is one FOP tensor (single-FOP plan)
+    or a list of FOP tensors (batched plan, lengths `n_chans`); synthetic
+    Exp(1) noise of the right shape is made when omitted.  `ta`: [H][T]
+    fp32 thresholds on the device (k + 6 sqrt(k) when omitted)."""
+    import torch
+
+    import paper_1805_12258_amd as hs
+
+    dev = torch.device("cuda")
+    props = torch.cuda.get_device_properties(dev)
+    cus = cus or props.multi_processor_count
+    tdt = {"f32": torch.float32, "f16": torch.float16, "bf16": torch.bfloat16}[dtype]
+    align = 4 if dtype == "f32" else 8
+    gen = torch.Generator(device=dev).manual_seed(12345)
+
+    def noise(n):
+        ld = (n + align - 1) // align * align
+        x = torch.empty((T, ld), dtype=torch.float32, device=dev).exponential_(1.0, generator=gen)
+        return (x * input_scale).to(tdt)
+
+    if ta is None:
+        ta = torch.tensor([[k + 6.0 * k ** 0.5] * T for k in range(1, H + 1)], dtype=torch.float32,
+                          device=dev)
+    single = n_chans is None
+    if fops is None:
+        fops = noise(N) if single else [noise(n) for n in n_chans]
+
+    if single:
+        cap = 1 << 22
+        out = torch.empty((cap, 2), dtype=torch.int32, device=dev)
+        counts = torch.empty(H + 1, dtype=torch.int64, device=dev)
+    else:
+        caps = [int(2 * 180000 * n / (1 << 20)) + 4096 for n in n_chans]
+        offs = [0]
+        for c in caps[:-1]:
+            offs.append(offs[-1] + c)
+        out = torch.empty((sum(caps), 2), dtype=torch.int32, device=dev)
+        counts = torch.empty((len(n_chans), H + 1), dtype=torch.int64, device=dev)
+        ptrs = torch.tensor([x.data_ptr() for x in fops], dtype=torch.int64, device=dev)
+        lds = torch.tensor([x.stride(0) for x in fops], dtype=torch.int64, device=dev)
+        offs_d = torch.tensor(offs, dtype=torch.int64, device=dev)
+        caps_d = torch.tensor(caps, dtype=torch.int64, device=dev)
+
+    def timer(cfg):
+        try:
+            plan = hs.Plan(T, 0 if not single else N, H, dtype=dtype, input_scale=input_scale,
+                           n_chans=n_chans, **cfg)
+        except hs.HsError:
+            return None
+        if single:
+            def run():
+                hs.hs_detect(plan.handle, fops, fops.stride(0), ta, out, cap, counts)
+        else:
+            def run():
+                hs.hs_detect_batched(plan.handle, ptrs, lds, ta, out, offs_d, caps_d, counts)
+        run()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            run()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    best, best_ms, tried = search(candidates(single, cus), timer)
+    if cache:
+        key = cache_key(T, N, H, dtype, n_chans, props.name)
+        store_cache(cache, key, {"config": best, "ms": best_ms})
+    return best, best_ms, tried
+
+
+def tuned_plan(T, N, H, dtype="f32", input_scale=1.0, n_chans=None, cache=DEFAULT_CACHE, **tune_kw):
+    """A Plan with the cached best configuration for this shape and device,
+    tuning first when the cache has none."""
+    import torch
+
+    import paper_1805_12258_amd as hs
+
+    key = cache_key(T, N, H, dtype, n_chans, torch.cuda.get_device_properties(torch.device("cuda")).name)
+    entry = load_cache(cache).get(key) if cache else None
+    if entry is None:
+        cfg, _, _ = tune(T, N, H, dtype, input_scale, n_chans, cache=cache, **tune_kw)
+    else:
+        cfg = entry["config"]
+    return hs.Plan(T, 0 if n_chans is not None else N, H, dtype=dtype, input_scale=input_scale,
+                   n_chans=n_chans, **cfg), cfg

@@ -253,3 +253,20 @@ def test_select_top_capped(T, N, H, n_cands):
     # an empty list gives zero counts
     got, cnt = plan.select_top(out, 0, 4)
     assert np.array_equal(cnt.cpu().numpy(), np.zeros(H, dtype=np.int64))
+
+
+def test_autotuned_plan_matches_oracle(tmp_path):
+    """The autotuner picks among configurations with identical results: the
+    tuned plan (from a fresh cache, then from the cache) gives the oracle's
+    candidates."""
+    from paper_1805_12258_amd import autotune as at
+    T, N, H = 21, 256 * 96 + 5, 8
+    x = exp_plane(T, N, 77)
+    ta = random_thresholds(H, T, 78)
+    dev, store = padded_device(x)
+    cache = str(tmp_path / "tune.json")
+    best, ms, tried = at.tune(T, N, H, fops=dev, ta=torch.from_numpy(ta).cuda(), reps=1, cache=cache)
+    assert ms > 0 and len(tried) == len(at.candidates(True))
+    plan, cfg = at.tuned_plan(T, N, H, cache=cache)
+    assert cfg == best
+    assert_same_candidates(gpu_detect(plan, dev, ta, capacity=H * T * N), oracle_detect_sorted(store, H, ta))

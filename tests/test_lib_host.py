@@ -163,3 +163,26 @@ def test_tile_schedule(T, N):
     # contiguous chunks on request, and for batched plans
     assert hs.hs_plan_schedule(hs.Plan(T, N, 8, schedule=1).handle) == []
     assert hs.hs_plan_schedule(hs.Plan(T, 0, 8, n_chans=[N, N]).handle) == []
+
+
+def test_autotune_search_and_cache(tmp_path):
+    """The tuner keeps the fastest valid configuration (ties: the earlier),
+    skips invalid ones, and the cache round-trips."""
+    from paper_1805_12258_amd import autotune as at
+    cfgs = at.candidates(True, cus=256)
+    assert len(cfgs) == len(at.TILE_ROWS) * len(at.GRID_FACTORS) * len(at.SCHEDULES)
+    assert all(c["schedule"] == 0 for c in at.candidates(False, cus=256))
+    times = {i: 5.0 - (i % 4) for i in range(len(cfgs))}
+    times[7] = None
+    best, ms, tried = at.search(cfgs, lambda c: times[cfgs.index(c)])
+    assert ms == min(v for v in times.values() if v is not None)
+    assert cfgs.index(best) == min(i for i, v in times.items() if v == ms)
+    assert len(tried) == len(cfgs)
+    with pytest.raises(RuntimeError):
+        at.search(cfgs[:2], lambda c: None)
+    path = str(tmp_path / "tune.json")
+    key = at.cache_key(85, 1 << 21, 8, "f32", None, "gfx950")
+    assert key != at.cache_key(85, 0, 8, "f32", [1 << 19, 1 << 20], "gfx950")
+    at.store_cache(path, key, {"config": best, "ms": ms})
+    assert at.load_cache(path)[key]["config"] == best
+    assert at.load_cache(str(tmp_path / "missing.json")) == {}
