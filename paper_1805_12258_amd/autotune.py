@@ -16,7 +16,8 @@ import os
 DEFAULT_CACHE = os.path.join(os.path.expanduser("~"), ".cache", "hs_autotune.json")
 
 TILE_ROWS = (0, 24, 16)                 # 0: the planner's choice (32)
-GRID_FACTORS = (0, 1, 3)                # 0: occupancy; else blocks per CU
+GRID_FACTORS = (0, 1)                   # 0: occupancy; else blocks per CU (resident grids only)
+MARGIN = 0.02                           # a candidate must beat the incumbent by 2 %
 SCHEDULES = (0, 1)
 
 
@@ -58,15 +59,17 @@ def store_cache(path, key, entry):
     os.replace(tmp, path)
 
 
-def search(configs, timer):
+def search(configs, timer, margin=MARGIN):
     """The fastest configuration: timer(cfg) returns milliseconds, or None
-    when the configuration is not valid for the shape (skipped).  Ties keep
-    the earlier configuration."""
+    when the configuration is not valid for the shape (skipped).  The first
+    valid configuration (the planner's defaults come first) is the
+    incumbent; a later one replaces it only when faster by more than
+    `margin`, so timing noise does not move the choice."""
     best, best_ms, tried = None, None, []
     for cfg in configs:
         ms = timer(cfg)
         tried.append({"config": cfg, "ms": ms})
-        if ms is not None and (best_ms is None or ms < best_ms):
+        if ms is not None and (best_ms is None or ms < best_ms * (1.0 - margin)):
             best, best_ms = cfg, ms
     if best is None:
         raise RuntimeError("no valid configuration")

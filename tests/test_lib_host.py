@@ -172,12 +172,17 @@ def test_autotune_search_and_cache(tmp_path):
     cfgs = at.candidates(True, cus=256)
     assert len(cfgs) == len(at.TILE_ROWS) * len(at.GRID_FACTORS) * len(at.SCHEDULES)
     assert all(c["schedule"] == 0 for c in at.candidates(False, cus=256))
+    assert cfgs[0] == {"tile_rows": 0, "persistent_blocks": 0, "schedule": 0}   # planner defaults first
     times = {i: 5.0 - (i % 4) for i in range(len(cfgs))}
-    times[7] = None
-    best, ms, tried = at.search(cfgs, lambda c: times[cfgs.index(c)])
+    times[3] = None
+    best, ms, tried = at.search(cfgs, lambda c: times[cfgs.index(c)], margin=0.0)
     assert ms == min(v for v in times.values() if v is not None)
     assert cfgs.index(best) == min(i for i, v in times.items() if v == ms)
     assert len(tried) == len(cfgs)
+    # within the margin the incumbent stays
+    near = {i: 5.0 - 0.005 * i for i in range(len(cfgs))}      # at most 1.1 % faster
+    best, ms, _ = at.search(cfgs, lambda c: near[cfgs.index(c)], margin=0.02)
+    assert best == cfgs[0] and ms == 5.0
     with pytest.raises(RuntimeError):
         at.search(cfgs[:2], lambda c: None)
     path = str(tmp_path / "tune.json")
