@@ -27,14 +27,16 @@
  *    multiple of 4 (fp32) or 8 (fp16, bf16) elements; HS_ERR_INVALID
  *    otherwise.  Reduced-precision storage holds power * input_scale;
  *    thresholds and reported powers are in unscaled units.
- *  * Every pointer argument except hs_plan_desc.n_chans and the host count
- *    array of hs_check_counts is DEVICE memory owned by the caller.  The
- *    library never frees caller memory.
+ *  * Every pointer argument except hs_plan_desc.n_chans, the host count
+ *    array of hs_check_counts and the output of hs_plan_schedule is DEVICE
+ *    memory owned by the caller.  The library never frees caller memory.
  *  * `stream` is a hipStream_t (NULL = the default stream).  Calls enqueue
  *    work and return without waiting; the status covers argument checks and
  *    the launch only.  Output is valid once the stream has been synchronised.
- *  * A plan is immutable after creation and may be used from several
- *    streams at once: all per-call state lives in caller buffers.
+ *  * A plan's results do not change after creation and it may be used from
+ *    several streams and threads at once: all per-call state lives in caller
+ *    buffers (the one-time device copy of a plan's tables is made under a
+ *    lock).
  *  * No C++ exception crosses this interface.
  */
 #ifndef HS_H
