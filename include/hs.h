@@ -130,7 +130,8 @@ int64_t hs_plan_schedule(const hs_plan* plan, uint32_t* words, int64_t capacity)
  * device that is not under stream capture copies the plan's tile schedule
  * (4 bytes per full tile, freed by hs_plan_destroy) to that device; before
  * that copy exists the kernels walk the tiles in contiguous chunks, with
- * the same results.  Make one eager call before capturing a graph to get the
+ * the same results, as they do for a stream of another device than the
+ * current one.  Make one eager call before capturing a graph to get the
  * scheduled order inside the graph. */
 
 /* All harmonic planes (Eq. 1-2), materialised: hp is [n_hp][N_temp][N_chan]
@@ -188,7 +189,8 @@ hs_status hs_detect_singlehp(const hs_plan* plan, const float* fop, int64_t ld, 
  *   counts      [n_fops][n_hp + 1] per-FOP counts as in hs_detect
  * Alignment rules of the FOP apply to every FOP (checked on the device:
  * misaligned FOPs are skipped and their total count is set to -1).
- * Batched plans only. */
+ * `stream` must belong to the current device (HS_ERR_INVALID otherwise):
+ * the plan's tables are copied per device.  Batched plans only. */
 hs_status hs_detect_batched(const hs_plan* plan, const void* const* fops, const int64_t* lds,
                             const float* ta, hs_cand* out, const int64_t* out_offsets,
                             const int64_t* caps, int64_t* counts, void* stream);

@@ -108,6 +108,11 @@ const uint32_t* device_sched(const hs_plan* p, hipStream_t stream)
     if (p->sched.empty()) return nullptr;
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return nullptr;
+    if (stream) {
+        // a stream of another device: no table (its pointer would be foreign)
+        hipDevice_t sd = 0;
+        if (hipStreamGetDevice(stream, &sd) != hipSuccess || (int)sd != dev) return nullptr;
+    }
     std::lock_guard<std::mutex> g(p->mu);
     if (!p->d_sched[dev]) {
         hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
@@ -381,6 +386,11 @@ hs_status hs_detect_batched(const hs_plan* p, const void* const* fops, const int
     try {
         int dev = 0;
         if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return HS_ERR_HIP;
+        if (stream) {
+            // the plan's tables are per device: the stream must belong to the current one
+            hipDevice_t sd = 0;
+            if (hipStreamGetDevice((hipStream_t)stream, &sd) != hipSuccess || (int)sd != dev) return HS_ERR_INVALID;
+        }
         int64_t* tables = nullptr;
         {
             std::lock_guard<std::mutex> g(p->mu);
