@@ -270,3 +270,24 @@ def test_autotuned_plan_matches_oracle(tmp_path):
     plan, cfg = at.tuned_plan(T, N, H, cache=cache)
     assert cfg == best
     assert_same_candidates(gpu_detect(plan, dev, ta, capacity=H * T * N), oracle_detect_sorted(store, H, ta))
+
+
+def test_detect_on_side_stream():
+    """hs_detect on a non-default stream of the current device (the plan's
+    tile schedule is copied for that device): the oracle's candidates."""
+    T, N, H = 21, 256 * 64, 8
+    x = exp_plane(T, N, 31)
+    ta = random_thresholds(H, T, 32)
+    dev, store = padded_device(x)
+    plan = hs.Plan(T, N, H)
+    s = torch.cuda.Stream()
+    t = torch.from_numpy(np.ascontiguousarray(ta, dtype=np.float32)).cuda()
+    torch.cuda.synchronize()
+    with torch.cuda.stream(s):
+        out, counts = plan.detect(dev, t, capacity=H * T * N, stream=s)
+    s.synchronize()
+    counts = counts.cpu().numpy()
+    n = int(counts[-1])
+    a = out[:n].cpu().numpy()
+    got = (a[:, 0].view(np.uint32).copy(), a[:, 1].view(np.float32).copy(), counts)
+    assert_same_candidates(got, oracle_detect_sorted(store, H, ta))
