@@ -343,6 +343,39 @@ def main():
         "plane_points_per_s": H * points / (r["ms_per_step"] * 1e-3),
     }
 
+    # materialised planes (hs_sum): 4 B read + 4H B written per point
+    hp = torch.empty((H, T, N), dtype=torch.float32, device=dev)
+    ld = fop.stride(0)
+    hs.hs_sum(plan.handle, fop, ld, hp)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(10):
+        hs.hs_sum(plan.handle, fop, ld, hp)
+    e1.record()
+    torch.cuda.synchronize()
+    sum_ms = e0.elapsed_time(e1) / 10
+    sum_bytes = (4 + 4 * H) * points
+    line["sum"] = {"ms": sum_ms, "bytes_per_point": 4 + 4 * H,
+                   "gbs": sum_bytes / (sum_ms * 1e-3) / 1e9,
+                   "frac": sum_bytes / (sum_ms * 1e-3) / 1e9 / HBM_PEAK_GBS}
+    del hp
+
+    # canonical order of the full candidate list (hs_sort_candidates)
+    n_all = int(ref_counts[-1].item())
+    srt = ref_out[:n_all].clone()
+    srt_work = torch.empty(max(hs.hs_sort_workspace_bytes(n_all), 1), dtype=torch.uint8, device=dev)
+    copies = [srt.clone() for _ in range(6)]
+    hs.hs_sort_candidates(copies.pop(), n_all, srt_work)          # warm-up (first use loads the kernels)
+    torch.cuda.synchronize()
+    e0.record()
+    for c in copies:
+        hs.hs_sort_candidates(c, n_all, srt_work)
+    e1.record()
+    torch.cuda.synchronize()
+    line["sort"] = {"candidates": n_all, "ms": e0.elapsed_time(e1) / len(copies)}
+    del srt, srt_work, copies
+
     # per-plane capped lists (N_cand = 200) from the full candidate list
     n_all = int(ref_counts[-1].item())
     sel_out = torch.empty((H, 200, 2), dtype=torch.int32, device=dev)
