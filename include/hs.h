@@ -84,9 +84,17 @@ typedef struct hs_plan_desc {
     const int64_t* n_chans;    /* HOST array [n_fops]: bins of each FOP          */
     int32_t tile_rows;         /* tuning: rows per tile, 0 = planner's choice    */
     int32_t persistent_blocks; /* tuning: batched grid size, 0 = planner         */
-    int32_t schedule;          /* tuning, single FOP: 0 = full tiles dealt to    */
-                               /* the eight XCDs so that the sources of m = 2,   */
-                               /* 4, 8 are L2 hits; 1 = contiguous chunks        */
+    int32_t schedule;          /* tuning: which detection kernel and order.      */
+                               /* 0 = planner's choice: the strip walk for       */
+                               /* 16-bit storage or more than 8 planes, the tile */
+                               /* kernel otherwise; 4 = strip walk; 2 = tile     */
+                               /* kernel (walk units and tiles dealt to the      */
+                               /* eight XCDs so that sources are L2 hits);       */
+                               /* 1 = strip walk, 3 = tile kernel, both in       */
+                               /* increasing order (contiguous chunks).  The     */
+                               /* walk needs N_temp >= 2 and a threshold table   */
+                               /* of at most 16 KB; otherwise the tile kernel    */
+                               /* runs.  Results do not depend on it.            */
 } hs_plan_desc;
 
 /* Geometry chosen by the planner (host values; no GPU needed). */
@@ -103,10 +111,12 @@ typedef struct hs_plan_info {
     int32_t src_rows[17];       /* src_rows[m]: distinct source rows of stretch  */
                                 /* factor m over one full-height tile            */
     int64_t staged_words;       /* source words staged per full tile, m >= 2     */
+    int32_t detector;           /* detection kernel: 1 strip walk, 0 tile kernel */
 } hs_plan_info;
 
 /* Create a plan.  Validates the shapes (HS_ERR_INVALID: N_temp < 1, n_hp
- * outside 1..16, unknown dtype, input_scale not a power of two, n_fops < 0,
+ * outside 1..16, unknown dtype, input_scale not a power of two, n_fops
+ * outside 0..65535,
  * a bin count < 1, or a candidate word wider than 32 bits, i.e.
  * ceil(log2 N_temp) + ceil(log2 N_hp) + ceil(log2 N_chan) > 32).  Host only:
  * touches no GPU. */
@@ -125,6 +135,16 @@ hs_status hs_plan_info_get(const hs_plan* plan, hs_plan_info* info);
  * NULL when capacity is 0) and returns n, the schedule's length in words
  * (0: the plan walks tiles in contiguous chunks), or -1 for a NULL plan. */
 int64_t hs_plan_schedule(const hs_plan* plan, uint32_t* words, int64_t capacity);
+
+/* Copy the plan's device tables (unit schedule and row table of the
+ * detection kernel, tile schedule of the other kernels) to the current
+ * device, synchronously.  Every call makes this copy itself on first use on
+ * a device, except under stream capture: a detection call (hs_detect,
+ * hs_detect_batched) being captured on a device that has no copy yet returns
+ * HS_ERR_INVALID, so call this (or make one eager call) before capturing a
+ * graph.  The copy is freed by hs_plan_destroy.  HS_ERR_NOMEM / HS_ERR_HIP
+ * on allocation or copy failure. */
+hs_status hs_plan_upload(const hs_plan* plan);
 
 /* Single-FOP calls (hs_sum, hs_detect, hs_lse_*): the first such call on a
  * device that is not under stream capture copies the plan's tile schedule

@@ -58,7 +58,7 @@ class hs_plan_info(ctypes.Structure):
                 ("tile_bins", ctypes.c_int32), ("tile_rows", ctypes.c_int32),
                 ("row_blocks", ctypes.c_int32), ("lds_bytes", ctypes.c_int32),
                 ("tiles_total", ctypes.c_int64), ("src_rows", ctypes.c_int32 * 17),
-                ("staged_words", ctypes.c_int64)]
+                ("staged_words", ctypes.c_int64), ("detector", ctypes.c_int32)]
 
 
 _P = ctypes.c_void_p
@@ -68,6 +68,7 @@ _SIG = {
     "hs_plan_destroy": ([_P], ctypes.c_int),
     "hs_plan_info_get": ([_P, ctypes.POINTER(hs_plan_info)], ctypes.c_int),
     "hs_plan_schedule": ([_P, ctypes.POINTER(ctypes.c_uint32), _I64], _I64),
+    "hs_plan_upload": ([_P], ctypes.c_int),
     "hs_sum": ([_P, _P, _I64, _P, _P], ctypes.c_int),
     "hs_detect": ([_P, _P, _I64, _P, _P, _I64, _P, _P], ctypes.c_int),
     "hs_detect_batched": ([_P, _P, _P, _P, _P, _P, _P, _P, _P], ctypes.c_int),
@@ -150,6 +151,11 @@ def hs_plan_create(n_temp, n_chan=0, n_hp=8, dtype="f32", input_scale=1.0, n_cha
 
 def hs_plan_destroy(handle):
     _check(_c_hs_plan_destroy(handle), "hs_plan_destroy")
+
+
+def hs_plan_upload(handle):
+    """Copy the plan's device tables to the current device (synchronous)."""
+    _check(_c_hs_plan_upload(handle), "hs_plan_upload")
 
 
 def hs_plan_info_get(handle):

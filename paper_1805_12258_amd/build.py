@@ -50,9 +50,23 @@ def build(force=True, jobs=None, verbose=True):
     """Compile every source and link libhs.so.  Returns the library path."""
     os.makedirs(BUILD, exist_ok=True)
     hip, cpp = sources()
-    headers = [os.path.join(ROOT, "include", "hs.h")] + \
-        [os.path.join(CSRC, f) for f in os.listdir(CSRC) if f.endswith(".h")]
-    hdr_time = max(os.path.getmtime(h) for h in headers)
+    def dep_time(path, seen=None):
+        """Latest modification time of a source and the local headers it
+        includes (transitively)."""
+        seen = set() if seen is None else seen
+        if path in seen or not os.path.exists(path):
+            return 0.0
+        seen.add(path)
+        t = os.path.getmtime(path)
+        for line in open(path):
+            line = line.strip()
+            if line.startswith("#include \""):
+                name = line.split('"')[1]
+                for d in (CSRC, os.path.join(ROOT, "include")):
+                    if os.path.exists(os.path.join(d, name)):
+                        t = max(t, dep_time(os.path.join(d, name), seen))
+                        break
+        return t
     tasks = []
     for f in hip:
         tasks.append((f, os.path.join(BUILD, f + ".o"), DEVICE_FLAGS))
@@ -61,7 +75,7 @@ def build(force=True, jobs=None, verbose=True):
     todo = []
     for src, obj, flags in tasks:
         stale = (not os.path.exists(obj) or
-                 os.path.getmtime(obj) < max(os.path.getmtime(os.path.join(CSRC, src)), hdr_time))
+                 os.path.getmtime(obj) < dep_time(os.path.join(CSRC, src)))
         if force or stale:
             todo.append((src, obj, flags))
     # the largest translation units first (more planes unroll to more code)

@@ -99,6 +99,194 @@ std::vector<uint32_t> build_schedule(int64_t n_full, int row_blocks)
     return out;
 }
 
+// Strip order of the walk kernel for one FOP of n_strips strips of 256 bins
+// (the kernel side is described in hs_walk_impl.h).  Strip x >= 8 lies in
+// octave L = floor(log2 x) at position (x - 2^L) / 2^L; its list is the three
+// bits after the leading one, and dividing x by 2, 4 or 8 keeps both the list
+// and the position scaled to the top octave.  Strips are ordered by that
+// position, then by octave (x/8, x/4, x/2 just before x), then by index.
+// lists == 8: one list per XCD; lists == 1: one list of all strips.
+std::vector<std::vector<uint32_t>> walk_strip_lists(int64_t n_strips, int lists, bool linear = false)
+{
+    std::vector<std::vector<uint32_t>> out(lists);
+    if (n_strips < 1) return out;
+    if (linear) {
+        // increasing strip order, dealt to the lists in turn
+        for (int64_t x = 0; x < n_strips; ++x) out[x % lists].push_back((uint32_t)x);
+        return out;
+    }
+    int top = 0;
+    while (((int64_t)2 << top) <= n_strips - 1) ++top;
+    struct E { int64_t key; int L; int64_t x; };
+    std::vector<E> l[8];
+    for (int64_t x = 0; x < n_strips; ++x) {
+        if (x < 8) {
+            l[lists == 8 ? x : 0].push_back({0, -1, x});
+            continue;
+        }
+        int L = 3;
+        while (((int64_t)2 << L) <= x) ++L;
+        const int64_t off = x - ((int64_t)1 << L);
+        const int k = (int)(off >> (L - 3));
+        const int64_t pos = off & (((int64_t)1 << (L - 3)) - 1);
+        l[lists == 8 ? k : 0].push_back({(pos << (top - L)) << 3 | k, L, x});
+    }
+    for (int k = 0; k < lists; ++k) {
+        std::sort(l[k].begin(), l[k].end(), [](const E& a, const E& b) {
+            if (a.key != b.key) return a.key < b.key;
+            if (a.L != b.L) return a.L < b.L;
+            return a.x < b.x;
+        });
+        for (const E& e : l[k]) out[k].push_back((uint32_t)e.x);
+    }
+    return out;
+}
+
+// Walk tables of a plan: units (band << 24) | strip for every band of every
+// strip; a single FOP spreads its strips over eight XCD lists, a batch puts
+// each FOP whole on one XCD (longest first onto the least loaded XCD).
+// Device layout: xseg [9] u32 | rowmask [T] u32 | seg [n_seg][4] i32 |
+// n_chans [n_fops] i64 | entries u32.
+void build_walk(hs_plan* p, bool linear)
+{
+    const int T = (int)p->T;
+    const int c = T / 2;
+    // the two half-planes as bands when each has at least kWalkDepth rows
+    // (the kernel keeps that many rows in flight and starts at most one unit
+    // inside them), else the full height as one band
+    p->band_split = (c >= hsk::kWalkDepth && T - c >= hsk::kWalkDepth) ? c : 0;
+    const int bands = p->band_split > 0 ? 2 : 1;
+    std::vector<uint32_t> rowmask(T, 0u);
+    for (int r = 0; r < T; ++r)
+        for (int m = 2; m <= hsk::kMaxH; ++m)
+            if (((r - c) % m + m) % m == 0) rowmask[r] |= 1u << m;
+
+    std::vector<uint32_t> ent;
+    std::vector<int32_t> seg;   // 4 per segment
+    std::vector<uint32_t> xseg(9, 0);
+    auto add_units = [&](const std::vector<uint32_t>& strips) {
+        const size_t first = ent.size();
+        for (int b = 0; b < bands; ++b)
+            for (uint32_t x : strips) ent.push_back(((uint32_t)b << 24) | x);
+        return std::make_pair((int64_t)first, (int64_t)(ent.size() - first));
+    };
+    std::vector<int64_t> nchan;
+    if (p->n_fops == 0) {
+        const auto lists = walk_strip_lists((p->N + hsk::kWalkStripBins - 1) / hsk::kWalkStripBins, 8, linear);
+        for (int x = 0; x < 8; ++x) {
+            xseg[x] = (uint32_t)(seg.size() / 4);
+            const auto r = add_units(lists[x]);
+            if (r.second > 0) {
+                seg.insert(seg.end(), {0, (int32_t)r.first, 0, (int32_t)r.second});
+            }
+        }
+        xseg[8] = (uint32_t)(seg.size() / 4);
+    } else {
+        // one unit list per distinct length
+        std::vector<std::pair<int64_t, std::pair<int64_t, int64_t>>> by_len;   // N -> (first, count)
+        std::vector<std::pair<int64_t, int64_t>> fl(p->n_fops);
+        for (int f = 0; f < p->n_fops; ++f) {
+            const int64_t n = p->n_chans[f];
+            auto it = std::find_if(by_len.begin(), by_len.end(), [&](const auto& e) { return e.first == n; });
+            if (it == by_len.end()) {
+                const auto lists = walk_strip_lists((n + hsk::kWalkStripBins - 1) / hsk::kWalkStripBins, 1, linear);
+                by_len.push_back({n, add_units(lists[0])});
+                it = by_len.end() - 1;
+            }
+            fl[f] = it->second;
+        }
+        // whole FOPs to XCDs: longest first onto the least loaded
+        std::vector<int> order(p->n_fops);
+        for (int f = 0; f < p->n_fops; ++f) order[f] = f;
+        std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return fl[a].second > fl[b].second; });
+        std::vector<std::vector<int>> on(8);
+        int64_t load[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+        for (int f : order) {
+            int best = 0;
+            for (int x = 1; x < 8; ++x)
+                if (load[x] < load[best]) best = x;
+            on[best].push_back(f);
+            load[best] += fl[f].second;
+        }
+        for (int x = 0; x < 8; ++x) {
+            std::sort(on[x].begin(), on[x].end());
+            xseg[x] = (uint32_t)(seg.size() / 4);
+            int64_t pre = 0;
+            for (int f : on[x]) {
+                if (fl[f].second == 0) continue;
+                seg.insert(seg.end(), {(int32_t)f, (int32_t)fl[f].first, (int32_t)pre, (int32_t)(pre + fl[f].second)});
+                pre += fl[f].second;
+            }
+        }
+        xseg[8] = (uint32_t)(seg.size() / 4);
+        nchan = p->n_chans;
+    }
+
+    auto align = [](size_t x) { return (x + 255) & ~(size_t)255; };
+    p->off_xseg = 0;
+    p->off_rowmask = align(p->off_xseg + xseg.size() * 4);
+    p->off_seg = align(p->off_rowmask + rowmask.size() * 4);
+    p->off_nchan = align(p->off_seg + seg.size() * 4);
+    p->off_ent = align(p->off_nchan + nchan.size() * 8);
+    p->walk_tab.assign(align(p->off_ent + ent.size() * 4), 0);
+    std::memcpy(p->walk_tab.data() + p->off_xseg, xseg.data(), xseg.size() * 4);
+    std::memcpy(p->walk_tab.data() + p->off_rowmask, rowmask.data(), rowmask.size() * 4);
+    if (!seg.empty()) std::memcpy(p->walk_tab.data() + p->off_seg, seg.data(), seg.size() * 4);
+    if (!nchan.empty()) std::memcpy(p->walk_tab.data() + p->off_nchan, nchan.data(), nchan.size() * 8);
+    if (!ent.empty()) std::memcpy(p->walk_tab.data() + p->off_ent, ent.data(), ent.size() * 4);
+    p->walk_lds = hsk::walk_lds_bytes(T, p->H, p->dtype);
+    p->walk = true;
+}
+
+// Device copy of the walk tables on the current device.  Made by the first
+// call on a device that is not under stream capture (or by hs_plan_upload);
+// a captured call before that gets HS_ERR_INVALID, since a copy cannot be
+// made inside a graph.
+hs_status device_walk(const hs_plan* p, hipStream_t stream, const unsigned char** out)
+{
+    *out = nullptr;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return HS_ERR_HIP;
+    if (stream) {
+        // the tables are per device: the stream must belong to the current one
+        hipDevice_t sd = 0;
+        if (hipStreamGetDevice(stream, &sd) != hipSuccess || (int)sd != dev) return HS_ERR_INVALID;
+    }
+    std::lock_guard<std::mutex> g(p->mu);
+    if (!p->d_walk[dev]) {
+        hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+        if (hipStreamIsCapturing(stream, &cs) != hipSuccess) return HS_ERR_HIP;
+        if (cs != hipStreamCaptureStatusNone) return HS_ERR_INVALID;
+        unsigned char* d = nullptr;
+        if (hipMalloc(&d, p->walk_tab.size()) != hipSuccess) return HS_ERR_NOMEM;
+        if (hipMemcpy(d, p->walk_tab.data(), p->walk_tab.size(), hipMemcpyHostToDevice) != hipSuccess) {
+            (void)hipFree(d);
+            return HS_ERR_HIP;
+        }
+        p->d_walk[dev] = d;
+    }
+    *out = p->d_walk[dev];
+    return HS_OK;
+}
+
+hsk::WalkArgs walk_args(const hs_plan* p, const unsigned char* tab)
+{
+    hsk::WalkArgs a{};
+    a.T = (int32_t)p->T;
+    a.c = (int32_t)(p->T / 2);
+    a.band_split = p->band_split;
+    a.scale = p->scale;
+    a.inv_scale = 1.0f / p->scale;
+    a.s_row = p->s_row;
+    a.s_bin = p->s_bin;
+    a.xseg = reinterpret_cast<const uint32_t*>(tab + p->off_xseg);
+    a.rowmask = reinterpret_cast<const uint32_t*>(tab + p->off_rowmask);
+    a.seg = reinterpret_cast<const int32_t*>(tab + p->off_seg);
+    a.n_chans = reinterpret_cast<const int64_t*>(tab + p->off_nchan);
+    a.ent = reinterpret_cast<const uint32_t*>(tab + p->off_ent);
+    return a;
+}
+
 // Device copy of the plan's schedule on the current device, made by the
 // first call on that device that is not under stream capture; null when the
 // plan has none or no copy exists yet: the kernels then take contiguous
@@ -175,9 +363,9 @@ hs_status hs_plan_create(hs_plan** out, const hs_plan_desc* d)
         const float scale = d->input_scale == 0.0f ? 1.0f : d->input_scale;
         if (!is_pow2_scale(scale)) return HS_ERR_INVALID;
         if (d->dtype == HS_DTYPE_F32 && scale != 1.0f) return HS_ERR_INVALID;
-        if (d->n_fops < 0) return HS_ERR_INVALID;
+        if (d->n_fops < 0 || d->n_fops > 65535) return HS_ERR_INVALID;
         if (d->tile_rows < 0 || d->persistent_blocks < 0) return HS_ERR_INVALID;
-        if (d->schedule != 0 && d->schedule != 1) return HS_ERR_INVALID;
+        if (d->schedule < 0 || d->schedule > 4) return HS_ERR_INVALID;
 
         hs_plan* p = new hs_plan();
         p->T = d->n_temp;
@@ -217,9 +405,22 @@ hs_status hs_plan_create(hs_plan** out, const hs_plan_desc* d)
         p->row_blocks = (int)((p->T + R - 1) / R);
         p->lds_bytes = hsk::fused_lds_bytes((int)p->T, R, p->H, hsk::kModeDetect, elem_bytes(p->dtype));
 
+        // detection: the strip walk (XCD lists by octave position; increasing
+        // strip order for schedule 1) where its threshold table fits and it
+        // is the faster kernel, else the tile kernel.  Measured on 85 x 2^21
+        // planes, the walk wins with 16-bit storage and with more than eight
+        // planes, the tile kernel with fp32 storage up to eight: schedule 0
+        // picks by that rule, 1 and 4 ask for the walk, 2 and 3 for the tile
+        // kernel.  The tile kernels of the other calls use the XCD tile
+        // schedule for 0, 2 and 4, contiguous chunks for 1 and 3.
+        const bool walk_wins = p->dtype != HS_DTYPE_F32 || p->H > 8;
+        const bool want_walk = d->schedule == 1 || d->schedule == 4 || (d->schedule == 0 && walk_wins);
+        if (want_walk && hsk::walk_supported((int)p->T, p->H)) build_walk(p, d->schedule == 1);
+
         if (d->n_fops == 0) {
             p->tiles_total = p->row_blocks * bin_tiles(p->N);
-            if (d->schedule == 0) p->sched = build_schedule(p->N / hsk::kTileBins, p->row_blocks);
+            if (d->schedule == 0 || d->schedule == 2 || d->schedule == 4)
+                p->sched = build_schedule(p->N / hsk::kTileBins, p->row_blocks);
         } else {
             p->tile_prefix.resize(d->n_fops + 1);
             int64_t acc = 0;
@@ -245,10 +446,11 @@ hs_status hs_plan_destroy(hs_plan* p)
     int cur = -1;
     bool have_dev = hipGetDevice(&cur) == hipSuccess;
     for (int dev = 0; dev < 64; ++dev) {
-        if (p->d_tables[dev] || p->d_sched[dev]) {
+        if (p->d_tables[dev] || p->d_sched[dev] || p->d_walk[dev]) {
             if (have_dev) (void)hipSetDevice(dev);
             if (p->d_tables[dev]) (void)hipFree(p->d_tables[dev]);
             if (p->d_sched[dev]) (void)hipFree(p->d_sched[dev]);
+            if (p->d_walk[dev]) (void)hipFree(p->d_walk[dev]);
         }
     }
     if (have_dev && cur >= 0) (void)hipSetDevice(cur);
@@ -262,6 +464,22 @@ int64_t hs_plan_schedule(const hs_plan* p, uint32_t* words, int64_t capacity)
     const int64_t n = (int64_t)p->sched.size();
     if (words && capacity > 0) std::memcpy(words, p->sched.data(), (size_t)std::min(n, capacity) * 4);
     return n;
+}
+
+hs_status hs_plan_upload(const hs_plan* p)
+{
+    if (!p) return HS_ERR_INVALID;
+    try {
+        if (p->walk) {
+            const unsigned char* tab = nullptr;
+            const hs_status st = device_walk(p, nullptr, &tab);
+            if (st != HS_OK) return st;
+        }
+        (void)device_sched(p, nullptr);
+        return HS_OK;
+    } catch (...) {
+        return HS_ERR_HIP;
+    }
 }
 
 hs_status hs_plan_info_get(const hs_plan* p, hs_plan_info* info)
@@ -281,6 +499,7 @@ hs_status hs_plan_info_get(const hs_plan* p, hs_plan_info* info)
     info->row_blocks = p->row_blocks;
     info->lds_bytes = p->lds_bytes;
     info->tiles_total = p->tiles_total;
+    info->detector = p->walk ? 1 : 0;
     // distinct source rows of each stretch factor over the full column, and the
     // words one full-height tile at a 256-bin aligned position stages
     const int64_t c = p->T / 2;
@@ -317,15 +536,38 @@ hs_status hs_detect(const hs_plan* p, const void* fop, int64_t ld, const float* 
     if (!fop_ok(p, fop, ld, p->N)) return HS_ERR_INVALID;
     try {
         hipStream_t s = (hipStream_t)stream;
-        hipError_t e = hsk::launch_zero_i64(counts, p->H + 1, s);
-        if (e != hipSuccess) return HS_ERR_HIP;
-        hsk::TileArgs a = tile_args(p, fop, ld, s);
-        a.ta = ta;
-        a.out = out;
-        a.cap = capacity;
-        a.counts = reinterpret_cast<unsigned long long*>(counts);
-        return from_hip(hsk::launch_fused(hsk::kModeDetect, p->dtype, p->H, a, p->tiles_total,
-                                          persistent_grid(p, p->tiles_total), p->lds_bytes, s));
+        if (p->walk) {
+            const unsigned char* tab = nullptr;
+            const hs_status st = device_walk(p, s, &tab);
+            if (st != HS_OK) return st;
+            if (hsk::launch_zero_i64(counts, p->H + 1, s) != hipSuccess) return HS_ERR_HIP;
+            hsk::WalkArgs a = walk_args(p, tab);
+            a.fop = fop;
+            a.ld = ld;
+            a.N = (int32_t)p->N;
+            a.n_fops = 0;
+            a.ta = ta;
+            a.out = out;
+            a.cap = capacity;
+            a.counts = reinterpret_cast<unsigned long long*>(counts);
+            if (hsk::launch_walk(p->dtype, p->H, a, p->persistent_blocks, p->walk_lds, s) != hipSuccess)
+                return HS_ERR_HIP;
+        } else {
+            hipError_t e = hsk::launch_zero_i64(counts, p->H + 1, s);
+            if (e != hipSuccess) return HS_ERR_HIP;
+            hsk::TileArgs a = tile_args(p, fop, ld, s);
+            a.ta = ta;
+            a.out = out;
+            a.cap = capacity;
+            a.counts = reinterpret_cast<unsigned long long*>(counts);
+            if (hsk::launch_fused(hsk::kModeDetect, p->dtype, p->H, a, p->tiles_total,
+                                  persistent_grid(p, p->tiles_total), p->lds_bytes, s) != hipSuccess)
+                return HS_ERR_HIP;
+        }
+        if (capacity == 0) return HS_OK;
+        return from_hip(hsk::launch_plane_counts(out, nullptr, nullptr, capacity,
+                                                 reinterpret_cast<unsigned long long*>(counts), 1, p->H,
+                                                 p->s_bin, (1u << p->s_k) - 1u, s));
     } catch (...) {
         return HS_ERR_HIP;
     }
@@ -384,6 +626,27 @@ hs_status hs_detect_batched(const hs_plan* p, const void* const* fops, const int
     if (!p || p->n_fops < 1 || !fops || !lds || !ta || !out || !out_offsets || !caps || !counts)
         return HS_ERR_INVALID;
     try {
+        hipStream_t s = (hipStream_t)stream;
+        if (p->walk) {
+            const unsigned char* tab = nullptr;
+            const hs_status st = device_walk(p, s, &tab);
+            if (st != HS_OK) return st;
+            if (hsk::launch_zero_i64(counts, (int64_t)p->n_fops * (p->H + 1), s) != hipSuccess) return HS_ERR_HIP;
+            hsk::WalkArgs a = walk_args(p, tab);
+            a.n_fops = p->n_fops;
+            a.fops = fops;
+            a.lds = lds;
+            a.out_offsets = out_offsets;
+            a.caps = caps;
+            a.ta = ta;
+            a.out = out;
+            a.counts = reinterpret_cast<unsigned long long*>(counts);
+            if (hsk::launch_walk(p->dtype, p->H, a, p->persistent_blocks, p->walk_lds, s) != hipSuccess)
+                return HS_ERR_HIP;
+            return from_hip(hsk::launch_plane_counts(out, out_offsets, caps, 0,
+                                                     reinterpret_cast<unsigned long long*>(counts), p->n_fops,
+                                                     p->H, p->s_bin, (1u << p->s_k) - 1u, s));
+        }
         int dev = 0;
         if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return HS_ERR_HIP;
         if (stream) {
@@ -409,7 +672,6 @@ hs_status hs_detect_batched(const hs_plan* p, const void* const* fops, const int
             }
             tables = p->d_tables[dev];
         }
-        hipStream_t s = (hipStream_t)stream;
         hipError_t e = hsk::launch_zero_i64(counts, (int64_t)p->n_fops * (p->H + 1), s);
         if (e != hipSuccess) return HS_ERR_HIP;
         hsk::BatchArgs b{};
@@ -435,7 +697,10 @@ hs_status hs_detect_batched(const hs_plan* p, const void* const* fops, const int
         b.kmask = (1u << p->s_k) - 1u;
         b.table_whole = hsk::table_whole((int)p->T, p->H) ? 1 : 0;
         const int grid = persistent_grid(p, p->tiles_total);
-        return from_hip(hsk::launch_batched(p->dtype, p->H, b, grid, p->lds_bytes, s));
+        if (hsk::launch_batched(p->dtype, p->H, b, grid, p->lds_bytes, s) != hipSuccess) return HS_ERR_HIP;
+        return from_hip(hsk::launch_plane_counts(out, out_offsets, caps, 0,
+                                                 reinterpret_cast<unsigned long long*>(counts), p->n_fops, p->H,
+                                                 p->s_bin, b.kmask, s));
     } catch (...) {
         return HS_ERR_HIP;
     }

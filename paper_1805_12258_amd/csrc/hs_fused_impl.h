@@ -26,9 +26,11 @@
 // L2 hits.  Without a schedule, block b walks a contiguous chunk of tiles.
 //
 // Candidates: each wave appends its hits to a private LDS buffer (ballot +
-// mbcnt, no atomics) and keeps per-plane counts in scalar registers.  A full
-// buffer is written out with one global atomic per wave; per-plane counts
-// are reduced through LDS and added to global memory once per block and FOP.
+// mbcnt, no atomics).  A full buffer is written out with one global atomic
+// per wave that reserves its positions in the list, and the block's last
+// buffers with one atomic for the whole block.  Per-plane counts are formed
+// by a counting pass over the list afterwards (only candidates dropped for
+// lack of capacity are counted here).
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -144,7 +146,7 @@ struct Smem {
                                   // table covers the whole plane)
     uint64_t* cand;               // [kWaves][kWaveCandCap] per-wave candidate buffers
                                   // (bin word in the low half, power bits high)
-    int* cnt;                     // [kMaxH] per-plane counts of the block
+    int* cnt;                     // [kCntWords] bookkeeping of the block's candidate flush
     struct FlushParams* fp;       // where flushed candidates go
 };
 
@@ -153,7 +155,8 @@ struct Smem {
 struct FlushParams {
     hs_cand* out;
     int64_t cap;
-    unsigned long long* total;   // counts[H]
+    unsigned long long* counts;   // [H+1]: per-plane counts, then the total
+    int32_t H;
     int32_t s_bin;
     uint32_t kmask;
 };
@@ -181,7 +184,7 @@ __device__ __forceinline__ Smem carve(float* lds, int T, int R, bool whole)
     s.rowtab[1] = whole ? s.rowtab[0] : s.rowtab[0] + trows * row_table_stride(H);
     s.cand = reinterpret_cast<uint64_t*>(s.rowtab[1] + trows * row_table_stride(H));
     s.cnt = reinterpret_cast<int*>(s.cand + kWaves * kWaveCandCap);
-    s.fp = reinterpret_cast<FlushParams*>(s.cnt + kMaxH);
+    s.fp = reinterpret_cast<FlushParams*>(s.cnt + kCntWords);
     return s;
 }
 
@@ -223,74 +226,100 @@ __device__ __forceinline__ uint64_t read_first_u64(uint64_t x)
     return ((uint64_t)hi << 32) | lo;
 }
 
-// Write a wave's buffered candidates to global memory (one atomic per wave)
-// and count them per plane in the block's LDS counters (the plane is read
-// back from each candidate word).
-__device__ __forceinline__ void flush_wave(const uint64_t* wbuf, int n, hs_cand* out, int64_t cap,
-                                           unsigned long long* total, int* block_cnt, int s_bin,
-                                           uint32_t kmask)
+// Write a wave's buffered candidates to global memory (one atomic per wave
+// reserves their positions in the list).  The per-plane counts of the
+// entries that fit are formed afterwards from the list itself (a counting
+// pass); entries past the capacity are dropped, and only those are counted
+// here, per plane.
+__device__ __forceinline__ void store_cands(const uint64_t* wbuf, int n, unsigned long long base, hs_cand* out,
+                                            int64_t cap, unsigned long long* counts, int s_bin, uint32_t kmask)
 {
     const int lane = threadIdx.x & 63;
-    unsigned long long base = 0;
-    if (lane == 0) base = atomicAdd(total, (unsigned long long)n);
-    base = read_first_u64(base);
-    for (int e = lane; e < n; e += 64) {
-        const uint64_t c = wbuf[e];
-        atomicAdd(&block_cnt[((uint32_t)c >> s_bin) & kmask], 1);
-        if ((int64_t)(base + e) < cap) reinterpret_cast<uint64_t*>(out)[base + e] = c;
+    for (int e0 = 0; e0 < n; e0 += 64) {   // uniform trip count
+        const int e = e0 + lane;
+        if (e < n) {
+            const uint64_t c = wbuf[e];
+            if ((int64_t)(base + e) < cap) reinterpret_cast<uint64_t*>(out)[base + e] = c;
+            else atomicAdd(&counts[((uint32_t)c >> s_bin) & kmask], 1ull);
+        }
     }
 }
 
-// Add the block's per-plane counts to global memory and clear them.  Called
-// by the whole block; contains barriers.
-template <int H>
-__device__ __forceinline__ void flush_counts(const Smem& sh, unsigned long long* counts)
+__device__ __forceinline__ void flush_wave(const uint64_t* wbuf, int n, hs_cand* out, int64_t cap,
+                                           unsigned long long* counts, int H, int s_bin, uint32_t kmask)
 {
+    const int lane = threadIdx.x & 63;
+    unsigned long long base = 0;
+    if (lane == 0) base = atomicAdd(&counts[H], (unsigned long long)n);
+    base = read_first_u64(base);
+    store_cands(wbuf, n, base, out, cap, counts, s_bin, kmask);
+}
+
+// Flush every wave's buffer with one atomic for the whole block (called by
+// the whole block; contains barriers).  `n` is the calling wave's fill; the
+// block's bookkeeping uses the LDS words at sh.cnt.
+template <int H>
+__device__ __forceinline__ void flush_block(const Smem& sh, int n, unsigned long long* counts, hs_cand* out,
+                                            int64_t cap, int s_bin, uint32_t kmask)
+{
+    int* bf = sh.cnt;   // [0, kWaves): fills; [kWaves, 2 kWaves): offsets; then the base (2 words)
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     __syncthreads();
-    if (threadIdx.x < H) {
-        const int v = sh.cnt[threadIdx.x];
-        if (v) atomicAdd(&counts[threadIdx.x], (unsigned long long)v);
-        sh.cnt[threadIdx.x] = 0;
+    if (lane == 0) bf[wave] = n;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int acc = 0;
+        for (int w = 0; w < kWaves; ++w) {
+            bf[kWaves + w] = acc;
+            acc += bf[w];
+        }
+        const unsigned long long b = acc ? atomicAdd(&counts[H], (unsigned long long)acc) : 0ull;
+        bf[2 * kWaves] = (int)(uint32_t)b;
+        bf[2 * kWaves + 1] = (int)(uint32_t)(b >> 32);
     }
+    __syncthreads();
+    const unsigned long long base = ((unsigned long long)(uint32_t)bf[2 * kWaves + 1] << 32) |
+                                    (uint32_t)bf[2 * kWaves];
+    store_cands(sh.cand + wave * kWaveCandCap, n, base + (unsigned long long)bf[kWaves + wave], out, cap, counts,
+                s_bin, kmask);
     __syncthreads();
 }
 
 // Out-of-line flush of the calling wave's buffer (n entries): the rare path
 // inside the row loop, kept out of line so the loop stays small.
-__device__ __noinline__ void flush_call(int n, const uint64_t* wbuf, int* block_cnt,
-                                        const FlushParams* fp)
+__device__ __noinline__ void flush_call(int n, const uint64_t* wbuf, const FlushParams* fp)
 {
-    flush_wave(wbuf, n, fp->out, fp->cap, fp->total, block_cnt, fp->s_bin, fp->kmask);
+    flush_wave(wbuf, n, fp->out, fp->cap, fp->counts, fp->H, fp->s_bin, fp->kmask);
 }
 
 __device__ __forceinline__ void set_flush_params(const Smem& sh, hs_cand* out, int64_t cap,
-                                                 unsigned long long* total, int s_bin, uint32_t kmask)
+                                                 unsigned long long* counts, int H, int s_bin, uint32_t kmask)
 {
     if (threadIdx.x == 0) {
         sh.fp->out = out;
         sh.fp->cap = cap;
-        sh.fp->total = total;
+        sh.fp->counts = counts;
+        sh.fp->H = H;
         sh.fp->s_bin = s_bin;
         sh.fp->kmask = kmask;
     }
 }
 
-// Fill at which a wave's buffer is flushed between tiles.
-constexpr int kFlushAt = 64;
-
 // Append the hits of one (row, plane) to the wave's LDS buffer.  Called by
 // the whole wave (uniform control flow): positions come from wave ballots.
-// A buffer without room for the V * 64 entries one call can add is flushed
-// first (one check per call keeps the inlined copies small).
+// `lanes` is the number of lanes with a hit: the call adds at most V * lanes
+// entries.  The buffer is written out only when that many might not fit, so
+// that a flush carries a nearly full buffer (each flush costs one atomic on
+// the list's shared counter).
 template <int V, int H>
-__device__ __forceinline__ void emit_hits(const float* acc, float t, int r, int k, int64_t jb,
+__device__ __forceinline__ void emit_hits(const float* acc, float t, int r, int k, int64_t jb, int lanes,
                                           const TileArgs& a, const Smem& sh, WaveState<H>& ws,
                                           uint64_t* wbuf)
 {
     const uint32_t hi = (uint32_t)(((uint64_t)r << a.s_row) | ((uint64_t)(k - 1) << a.s_bin));
-    static_assert(kWaveCandCap >= V * 64 + kFlushAt, "candidate buffer");
-    if (__builtin_expect(ws.n > kWaveCandCap - V * 64, 0)) {
-        flush_call(ws.n, wbuf, sh.cnt, sh.fp);
+    static_assert(kWaveCandCap >= V * 64, "candidate buffer");
+    if (__builtin_expect(ws.n + V * lanes > kWaveCandCap, 0)) {
+        flush_call(ws.n, wbuf, sh.fp);
         ws.n = 0;
     }
 #pragma unroll
@@ -305,16 +334,6 @@ __device__ __forceinline__ void emit_hits(const float* acc, float t, int r, int 
                 wbuf[ws.n + pre] = ((uint64_t)__float_as_uint(acc[v] * a.inv_scale) << 32) | (hi | (uint32_t)(jb + v));
             ws.n += __builtin_popcountll(mk);
         }
-    }
-}
-
-// Flush the wave's buffer once it holds kFlushAt entries (between tiles).
-template <int H>
-__device__ __forceinline__ void maybe_flush(const Smem& sh, WaveState<H>& ws)
-{
-    if (ws.n >= kFlushAt) {
-        flush_call(ws.n, sh.cand + (threadIdx.x >> 6) * kWaveCandCap, sh.cnt, sh.fp);
-        ws.n = 0;
     }
 }
 
@@ -625,8 +644,9 @@ __device__ __forceinline__ void compute_tile(const TileArgs& a, const RowGeo& g,
                 // cheap wave test first: the largest of the lane's kV sums
                 // (NaN operands are ignored by max and fail the compare)
                 const float mx = fmaxf(fmaxf(acc[0], acc[1]), fmaxf(acc[2], acc[3]));
-                if (__builtin_expect(__builtin_amdgcn_ballot_w64(mx > t) != 0, 0))
-                    emit_hits<kV, H>(acc, t, r, k, jb, a, sh, ws, wbuf);
+                const uint64_t any = __builtin_amdgcn_ballot_w64(mx > t);
+                if (__builtin_expect(any != 0, 0))
+                    emit_hits<kV, H>(acc, t, r, k, jb, __builtin_popcountll(any), a, sh, ws, wbuf);
             } else if constexpr (MODE == kModeLse) {
                 float xv[kV];
 #pragma unroll
@@ -761,7 +781,6 @@ __device__ __forceinline__ void run_full(const TileArgs& a, const TileSeq& q, co
             lds_barrier();
         }
         compute_tile<TIn, H, MODE, true>(a, gc, bt, sh, RAW ? sh.stage[0] : sh.stage[B], sh.rowtab[B], xc, ws);
-        if (MODE == kModeDetect) maybe_flush<H>(sh, ws);
         gc = gn; bt = bt1;
         return ++k < q.count;
     };
@@ -788,7 +807,6 @@ __device__ __forceinline__ void run_partial(const TileArgs& a, int64_t begin, in
         __builtin_amdgcn_s_waitcnt(0);
         __syncthreads();
         compute_tile<TIn, H, MODE, false>(a, g, n_full, sh, sh.stage[0], sh.rowtab[0], xa, ws);
-        if (MODE == kModeDetect) maybe_flush<H>(sh, ws);
     }
 }
 
@@ -875,7 +893,10 @@ __device__ __forceinline__ void block_chunk(int64_t n, int64_t& t_begin, int64_t
     t_end = t_begin + q + (b < r ? 1 : 0);
 }
 
-template <int H> constexpr int fused_min_waves() { return 1; }
+// Occupancy asked of the compiler: four waves per SIMD (at most 128 VGPRs)
+// where that needs no scratch, otherwise its own choice.
+template <int H> constexpr int fused_min_waves() { return H <= 8 ? 4 : 1; }
+template <int H> constexpr int batched_min_waves() { return H <= 4 ? 4 : 1; }
 
 template <typename TIn, int H, int MODE>
 __global__ __launch_bounds__(kThreads, fused_min_waves<H>()) void k_fused(TileArgs a, int64_t n_tiles)
@@ -892,13 +913,12 @@ __global__ __launch_bounds__(kThreads, fused_min_waves<H>()) void k_fused(TileAr
             ws.ls[k] = 0.0f;
         }
     }
-    if (threadIdx.x < kMaxH) sh.cnt[threadIdx.x] = 0;
     if (a.table_whole) build_whole_table<H, MODE>(a.T, a.R, a.c, a.ta, a.scale, sh.rowtab[0]);
 
     uint32_t voff[dma_slot_regs(H, EB)];
     dma_offsets<H, EB>(a.ld, voff);
 
-    if (MODE == kModeDetect) set_flush_params(sh, a.out, a.cap, &a.counts[H], a.s_bin, a.kmask);
+    if (MODE == kModeDetect) set_flush_params(sh, a.out, a.cap, a.counts, H, a.s_bin, a.kmask);
 
     if (a.sched) {
         // full tiles from the list of this block's XCD (blocks are dealt to
@@ -918,24 +938,19 @@ __global__ __launch_bounds__(kThreads, fused_min_waves<H>()) void k_fused(TileAr
         run_tiles<TIn, H, MODE>(a, t0, t1, sh, voff, ws);
     }
 
-    if constexpr (MODE == kModeDetect) {
-        if (ws.n) flush_wave(sh.cand + (threadIdx.x >> 6) * kWaveCandCap, ws.n, a.out, a.cap,
-                             &a.counts[H], sh.cnt, a.s_bin, a.kmask);
-        flush_counts<H>(sh, a.counts);
-    }
+    if constexpr (MODE == kModeDetect) flush_block<H>(sh, ws.n, a.counts, a.out, a.cap, a.s_bin, a.kmask);
     if constexpr (MODE == kModeLse) lse_block_pairs<H>(sh, ws, a);
 }
 
 // Batched persistent kernel: the grid walks the tiles of every FOP.
 template <typename TIn, int H>
-__global__ __launch_bounds__(kThreads, fused_min_waves<H>()) void k_batched(BatchArgs b)
+__global__ __launch_bounds__(kThreads, batched_min_waves<H>()) void k_batched(BatchArgs b)
 {
     extern __shared__ __align__(16) float lds[];
     constexpr int EB = sizeof(typename Io<TIn>::T);
     const Smem sh = carve<H, EB>(lds, b.T, b.R, b.table_whole != 0);
     WaveState<H> ws;
     ws.n = 0;
-    if (threadIdx.x < kMaxH) sh.cnt[threadIdx.x] = 0;
     constexpr int align_elems = sizeof(typename Io<TIn>::T) == 4 ? 4 : 8;
 
     int64_t t0, t1;
@@ -983,15 +998,11 @@ __global__ __launch_bounds__(kThreads, fused_min_waves<H>()) void k_batched(Batc
         } else {
             uint32_t voff[dma_slot_regs(H, EB)];
             dma_offsets<H, EB>(a.ld, voff);
-            set_flush_params(sh, a.out, a.cap, &a.counts[H], a.s_bin, a.kmask);
+            set_flush_params(sh, a.out, a.cap, a.counts, H, a.s_bin, a.kmask);
             // tiles of this FOP segment, numbered from the FOP's first tile
             run_tiles<TIn, H, kModeDetect>(a, tf - fb, fe - fb, sh, voff, ws);
-            if (ws.n) {
-                flush_wave(sh.cand + (threadIdx.x >> 6) * kWaveCandCap, ws.n, a.out, a.cap,
-                           &a.counts[H], sh.cnt, a.s_bin, a.kmask);
-                ws.n = 0;
-            }
-            flush_counts<H>(sh, a.counts);
+            flush_block<H>(sh, ws.n, a.counts, a.out, a.cap, a.s_bin, a.kmask);
+            ws.n = 0;
         }
         tf = fe;
     }

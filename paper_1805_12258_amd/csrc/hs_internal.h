@@ -22,9 +22,10 @@ constexpr int kWaves = 8;
 constexpr int kThreads = kWaves * kLanes;
 constexpr int kRowsPerWave = 4;
 constexpr int kMaxTileRows = kWaves * kRowsPerWave;   // 32
-constexpr int kWaveCandCap = 320;        // per-wave LDS candidate buffer (>= kV*64 + 64)
+constexpr int kWaveCandCap = 320;        // per-wave LDS candidate buffer (>= kV*64)
 constexpr int kMaxH = 16;
-constexpr int kFlushParamBytes = 32;     // candidate-output parameters kept in LDS
+constexpr int kCntWords = 32;            // block bookkeeping words of the candidate flush
+constexpr int kFlushParamBytes = 48;     // candidate-output parameters kept in LDS
 
 // Source words a tile needs per row of stretch factor m: the largest number
 // of distinct floor(j/m) over kTileBins consecutive bins starting at a
@@ -153,7 +154,7 @@ __host__ __device__ constexpr bool table_whole(int T, int H)
 __host__ __device__ constexpr int smem_tail_bytes(int T, int R, int H)
 {
     return (table_whole(T, H) ? T : 2 * R) * row_table_stride(H) * 4 +
-           kWaves * kWaveCandCap * 8 + kMaxH * 4 + kFlushParamBytes;
+           kWaves * kWaveCandCap * 8 + kCntWords * 4 + kFlushParamBytes;
 }
 
 __host__ __device__ inline int64_t floordiv(int64_t a, int64_t b)
@@ -225,6 +226,33 @@ struct BatchArgs {
     int32_t table_whole;
 };
 
+// Arguments of the strip-walk detection kernel (hs_walk_impl.h), for one FOP
+// (n_fops == 0: fop, ld, N, out, cap, counts) or a batch (n_fops >= 1: the
+// per-FOP device arrays; out, counts are the bases).
+struct WalkArgs {
+    const void* fop;
+    int64_t ld;
+    int32_t N;
+    int32_t n_fops;
+    const void* const* fops;      // [n_fops] device
+    const int64_t* lds;           // [n_fops] device
+    const int64_t* n_chans;       // [n_fops] device (plan table)
+    const int64_t* out_offsets;   // [n_fops] device
+    const int64_t* caps;          // [n_fops] device
+    int32_t T, c;                 // rows; row r holds template index r - c
+    int32_t band_split;           // bands [0, band_split) and [band_split, T); 0: one band
+    float scale, inv_scale;
+    const float* ta;              // [H][T] unscaled
+    hs_cand* out;
+    int64_t cap;
+    unsigned long long* counts;   // [H+1] (batch: [n_fops][H+1])
+    int32_t s_row, s_bin;
+    const uint32_t* rowmask;      // [T]: bit m set when floor((r-c)/m) changes at row r
+    const uint32_t* ent;          // schedule entries (band << 24) | strip
+    const int32_t* seg;           // [n_seg][4]: FOP, first entry, first index, end index
+    const uint32_t* xseg;         // [9]: segments of XCD x are [xseg[x], xseg[x+1])
+};
+
 enum Mode { kModeDetect = 0, kModeSum = 1, kModeLse = 2, kModeWeights = 3 };
 
 // Fused log-sum-exp: most blocks one launch may use (the partial pairs of
@@ -245,6 +273,20 @@ hipError_t launch_fused(int mode, int dtype, int H, const TileArgs& a, int64_t n
 hipError_t launch_batched(int dtype, int H, const BatchArgs& a, int grid, int lds_bytes,
                           hipStream_t s);
 hipError_t launch_zero_i64(int64_t* p, int64_t n, hipStream_t s);
+// Per-plane counts of stored candidates (after a detection kernel): lists at
+// out + out_offsets[f] with capacities caps[f] (or one list of capacity `cap`
+// when both are null), counts [n_lists][H+1].
+hipError_t launch_plane_counts(const hs_cand* out, const int64_t* out_offsets, const int64_t* caps, int64_t cap,
+                               unsigned long long* counts, int n_lists, int H, int s_bin, uint32_t kmask,
+                               hipStream_t s);
+
+// Strip-walk detection (hs_walk_*.hip): whether a plane's thresholds fit
+// the kernel's LDS table, LDS bytes of one block, and the launch.
+bool walk_supported(int T, int H);
+int walk_lds_bytes(int T, int H, int dtype);
+constexpr int kWalkStripBins = 256;
+constexpr int kWalkDepth = 2;        // rows in flight per wave; every band has at least this many rows
+hipError_t launch_walk(int dtype, int H, const WalkArgs& a, int grid, int lds_bytes, hipStream_t s);
 
 // Transpose of the plane map and the log-sum-exp statistic (hs_grad.hip).
 int64_t backward_partial_floats(int T, int H, int R, int64_t N);
@@ -281,9 +323,18 @@ struct hs_plan {
 
     std::vector<uint32_t> sched;         // single FOP: full-tile schedule (empty: chunks)
 
+    // Strip-walk detection: unit schedule and row table, host copy laid out
+    // as the device buffer (offsets in bytes), copied once per device.
+    bool walk = false;
+    int band_split = 0;
+    std::vector<unsigned char> walk_tab;
+    size_t off_xseg = 0, off_rowmask = 0, off_seg = 0, off_nchan = 0, off_ent = 0;
+    int walk_lds = 0;
+
     // Device copies of the batched tables and of the schedule, made at plan
     // creation on the current device or on first use per device.
     mutable std::mutex mu;
     mutable int64_t* d_tables[64] = {nullptr};
     mutable uint32_t* d_sched[64] = {nullptr};
+    mutable unsigned char* d_walk[64] = {nullptr};
 };

@@ -67,18 +67,19 @@ def test_row_blocked_tiles(T, N, H, rows):
 @pytest.mark.parametrize("T,N,H,blocks", [(85, 256 * 300 + 17, 8, 0), (33, 1 << 16, 16, 13),
                                            (21, 256 * 40, 8, 100), (85, 256 * 64, 8, 9)])
 def test_schedule_orders(T, N, H, blocks):
-    """The XCD schedule (default) and contiguous chunks give the oracle's
-    planes and candidates, also with grids that leave the eight lists
-    different numbers of blocks."""
+    """Both detection kernels (strip walk, tile kernel), in XCD order and in
+    increasing order, give the oracle's planes and candidates, also with
+    grids that leave the eight lists different numbers of blocks."""
     print("case", T, N, H, blocks, flush=True)
     x = exp_plane(T, N, 900 + blocks)
     ta = random_thresholds(H, T, N + blocks)
     dev, store = padded_device(x)
     want = oracle_detect_sorted(store, H, ta)
     ref = oracle.sum_f32(store.numpy(), H)
-    for sched in (0, 1):
+    for sched in (0, 1, 2, 3, 4):
         plan = hs.Plan(T, N, H, persistent_blocks=blocks, schedule=sched)
-        assert (len(hs.hs_plan_schedule(plan.handle)) > 0) == (sched == 0)
+        assert (len(hs.hs_plan_schedule(plan.handle)) > 0) == (sched in (0, 2, 4))
+        assert plan.info["detector"] == (1 if sched in (1, 4) or (sched == 0 and H > 8) else 0)
         assert_same_candidates(gpu_detect(plan, dev, ta, capacity=H * T * N), want)
         hp = plan.sum(dev).cpu().numpy()
         assert np.array_equal(hp.view(np.uint32), ref.view(np.uint32)), sched

@@ -165,6 +165,26 @@ def test_tile_schedule(T, N):
     assert hs.hs_plan_schedule(hs.Plan(T, 0, 8, n_chans=[N, N]).handle) == []
 
 
+def test_detector_choice():
+    """Schedule 0 picks the strip walk for 16-bit storage or more than eight
+    planes and the tile kernel otherwise; 1 and 4 ask for the walk, 2 and 3
+    for the tile kernel; a plane too short for the walk's pipeline (or with
+    a threshold table over 16 KB) gets the tile kernel whatever is asked."""
+    N = 1 << 16
+    def det(T, H, dtype="f32", sched=0):
+        sc = 1.0 if dtype == "f32" else 0.125
+        return hs.Plan(T, N, H, dtype=dtype, input_scale=sc, schedule=sched).info["detector"]
+    assert det(85, 8) == 0 and det(85, 1) == 0
+    assert det(85, 8, "f16") == 1 and det(85, 8, "bf16") == 1 and det(85, 9) == 1 and det(85, 16) == 1
+    assert [det(85, 8, "f32", s) for s in range(5)] == [0, 1, 0, 0, 1]
+    assert [det(85, 16, "f16", s) for s in range(5)] == [1, 1, 0, 0, 1]
+    assert det(1, 16) == 0 and det(1, 8, "f16", 4) == 0          # T < 2
+    assert det(257, 16, "f32", 4) == 0                            # 257 x 16 x 4 B > 16 KB
+    assert det(256, 16, "f32", 4) == 1
+    with pytest.raises(hs.HsError):
+        hs.Plan(85, N, 8, schedule=5)
+
+
 def test_autotune_search_and_cache(tmp_path):
     """The tuner keeps the fastest valid configuration (ties: the earlier),
     skips invalid ones, and the cache round-trips."""
