@@ -10,7 +10,9 @@ Two independent layers:
   Eq. 1-2 summed in the order of Algorithm 1 (k, i, j), in fp32 (the parity
   truth) and fp64 (the accuracy truth), threshold detection with the packed
   candidate word of Sec. III, the transpose (explicit scatter over
-  (k, i, j, m)) and the touch counts of Sec. IV-A.
+  (k, i, j, m)) and the touch counts of Sec. IV-A; and the fractional
+  variant HPF_k(i,j) = sum_{m=1..k} FOP(floor(m i/k), floor(m j/k)) (planes
+  in fp32 and fp64, detection).
 * ``brute`` (numpy): each point of each plane evaluated on its own from the
   definition, and Algorithm 2's loop order (j, i, k) in plain Python loops for
   tiny planes.  These pin the C layer.
@@ -56,11 +58,15 @@ def load_library(path):
     lib.hso_detect_f32.argtypes = [P, I64, I64, I64, I, P, ctypes.c_float, P, P, I64, P, I]
     lib.hso_vjp_f64.argtypes = [P, I64, I64, I, P]
     lib.hso_touch_counts.argtypes = [I64, I64, I, ctypes.c_uint32, P]
+    lib.hso_sum_frac_f32.argtypes = [P, I64, I64, I64, I, P]
+    lib.hso_sum_frac_f64.argtypes = [P, I64, I64, I64, I, P]
+    lib.hso_detect_frac_f32.argtypes = [P, I64, I64, I64, I, P, ctypes.c_float, P, P, I64, P]
     lib.hso_pack.argtypes = [I64, I, I64, I64, I]
     lib.hso_pack.restype = ctypes.c_uint32
     lib.hso_field_bits.argtypes = [I64, I64, I, P, P, P]
     for f in (lib.hso_sum_f32, lib.hso_sum_f64, lib.hso_detect_f32, lib.hso_vjp_f64,
-              lib.hso_touch_counts, lib.hso_field_bits):
+              lib.hso_touch_counts, lib.hso_field_bits, lib.hso_sum_frac_f32, lib.hso_sum_frac_f64,
+              lib.hso_detect_frac_f32):
         f.restype = I
     return lib
 
@@ -130,6 +136,51 @@ def detect_f32(fop, H, ta, scale=1.0, cap=None, n_chan=None, nthreads=1):
                                 _ptr(idx), _ptr(pw), cap, _ptr(counts), int(nthreads))
     if rc not in (0, -3):
         raise ValueError("hso_detect_f32 rc=%d" % rc)
+    n = min(int(counts[H]), cap)
+    return idx[:n].copy(), pw[:n].copy(), counts
+
+
+def sum_frac_f32(fop, H, n_chan=None):
+    """Fractional-variant planes [H][T][N] in fp32: HPF_k(i,j) = sum over
+    m = 1..k of FOP(floor(m i/k), floor(m j/k)), added in m order."""
+    fop = np.ascontiguousarray(fop, dtype=np.float32)
+    T, N, ld = _plane_args(fop, n_chan)
+    hp = np.empty((H, T, N), dtype=np.float32)
+    rc = _load().hso_sum_frac_f32(_ptr(fop), T, N, ld, H, _ptr(hp))
+    if rc != 0:
+        raise ValueError("hso_sum_frac_f32 rc=%d" % rc)
+    return hp
+
+
+def sum_frac_f64(fop, H, n_chan=None):
+    """Fractional-variant planes in fp64 from an fp64 copy of the input."""
+    fop = np.ascontiguousarray(fop, dtype=np.float64)
+    T, N, ld = _plane_args(fop, n_chan)
+    hp = np.empty((H, T, N), dtype=np.float64)
+    rc = _load().hso_sum_frac_f64(_ptr(fop), T, N, ld, H, _ptr(hp))
+    if rc != 0:
+        raise ValueError("hso_sum_frac_f64 rc=%d" % rc)
+    return hp
+
+
+def detect_frac_f32(fop, H, ta, scale=1.0, cap=None, n_chan=None):
+    """Candidates of the fractional-variant planes, in (k, row, bin) order,
+    with the word and counts of detect_f32."""
+    fop = np.ascontiguousarray(fop, dtype=np.float32)
+    T, N, ld = _plane_args(fop, n_chan)
+    ta = np.ascontiguousarray(ta, dtype=np.float32)
+    if ta.shape != (H, T):
+        raise ValueError("thresholds must be [H][T]")
+    if cap is None:
+        cap = H * T * N
+    cap = int(cap)
+    idx = np.empty(max(cap, 1), dtype=np.uint32)
+    pw = np.empty(max(cap, 1), dtype=np.float32)
+    counts = np.zeros(H + 1, dtype=np.int64)
+    rc = _load().hso_detect_frac_f32(_ptr(fop), T, N, ld, H, _ptr(ta), float(scale),
+                                     _ptr(idx), _ptr(pw), cap, _ptr(counts))
+    if rc not in (0, -3):
+        raise ValueError("hso_detect_frac_f32 rc=%d" % rc)
     n = min(int(counts[H]), cap)
     return idx[:n].copy(), pw[:n].copy(), counts
 

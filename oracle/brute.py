@@ -16,6 +16,11 @@ Each function is the definition written out with no blocking or reordering:
   and floor(j/m) = b, clipped to the plane.  It is a different formula from
   the scatter loop in ``hs_oracle.c`` and must agree with it.
 
+* :func:`frac_planes_int` and :func:`frac_point_py` are the fractional
+  variant HPF_k(i,j) = sum_{m=1..k} FOP(floor(m i/k), floor(m j/k)): the
+  first as whole-plane integer gathers (exact for integer-valued FOPs), the
+  second as a plain loop for one point.
+
 Rows: storage row r holds template index i = r - T//2.
 """
 import numpy as np
@@ -114,3 +119,29 @@ def vjp_boxsum_f64(g):
         np.add.at(blk.T, b, rows.T)
         d += blk
     return d
+
+
+def frac_planes_int(fop_int, H):
+    """HPF_1..HPF_H as [H][T][N] int64 from an integer-valued FOP, each plane
+    one integer gather-sum over its k fractions m/k (no rounding)."""
+    x = np.asarray(fop_int, dtype=np.int64)
+    T, N = x.shape
+    i = template_index(T)
+    j = np.arange(N, dtype=np.int64)
+    out = np.empty((H, T, N), dtype=np.int64)
+    for k in range(1, H + 1):
+        acc = np.zeros((T, N), dtype=np.int64)
+        for m in range(1, k + 1):
+            acc += x[np.ix_((m * i) // k + T // 2, (m * j) // k)]
+        out[k - 1] = acc
+    return out
+
+
+def frac_point_py(fop, k, r, j):
+    """HPF_k at storage row r, bin j in Python floats (fp64), plain loop."""
+    T = len(fop)
+    i = r - T // 2
+    s = 0.0
+    for m in range(1, k + 1):
+        s += float(fop[(m * i) // k + T // 2][(m * j) // k])
+    return s

@@ -19,6 +19,9 @@
  *   SP_m(i,j) = FOP(floor(i/m), floor(j/m))           (Sec. III, Eq. 1)
  *   HP_1 = FOP,  HP_k = HP_{k-1} + SP_k, k = 2..H    (Sec. III, Eq. 2)
  *   candidate: HP_k(i,j) > TA(k, i)                  (Sec. III, detection)
+ *   fractional variant (the incoherent-sum reading of "the k-th harmonic
+ *   plane sums the FOP at the fractions m/k of each point"; not Eq. 1-2):
+ *   HPF_k(i,j) = sum_{m=1..k} FOP(floor(m*i/k), floor(m*j/k)), m in order
  *   packed word CL1 = F * 2^(sk+sj) + (k-1) * 2^sj + B, where F is the
  *   storage row, B the bin, sj = ceil(log2 N), sk = ceil(log2 H); for the
  *   specification (85, 8, 2^21) this is the paper's F*2^24 + H*2^21 + B
@@ -241,4 +244,83 @@ int hso_touch_counts(int64_t T, int64_t N, int H, uint32_t kmask, int64_t* touch
                     touch[src_row(r, m, T) * N + fdiv(j, m)] += 1;
     }
     return 0;
+}
+
+/* ---------------------------------------------------------------------- */
+/* Fractional variant: HPF_k(i,j) = sum_{m=1..k} FOP(floor(m i/k),          */
+/* floor(m j/k)), each plane on its own (no recursion over k: the source    */
+/* points of plane k are the fractions m/k of (i, j), m = 1..k), terms      */
+/* added in the order m = 1, 2, ..., k with each partial sum rounded.       */
+/* Template indices are signed (i = r - T/2) and divided with the floor.    */
+/* ---------------------------------------------------------------------- */
+static int64_t frac_row(int64_t r, int64_t m, int64_t k, int64_t T)
+{
+    int64_t c = T / 2;
+    return fdiv(m * (r - c), k) + c;
+}
+
+static float frac_point_f32(const float* fop, int64_t ld, int64_t T, int64_t r, int64_t j, int k)
+{
+    float v = 0.0f;
+    for (int m = 1; m <= k; m++) {
+        float x = fop[frac_row(r, m, k, T) * ld + fdiv((int64_t)m * j, k)];
+        v = (m == 1) ? x : v + x;
+    }
+    return v;
+}
+
+int hso_sum_frac_f32(const float* fop, int64_t T, int64_t N, int64_t ld, int H, float* hp)
+{
+    if (T < 1 || N < 1 || H < 1 || ld < N) return -1;
+    for (int k = 1; k <= H; k++)
+        for (int64_t r = 0; r < T; r++)
+            for (int64_t j = 0; j < N; j++)
+                hp[((int64_t)(k - 1) * T + r) * N + j] = frac_point_f32(fop, ld, T, r, j, k);
+    return 0;
+}
+
+int hso_sum_frac_f64(const double* fop, int64_t T, int64_t N, int64_t ld, int H, double* hp)
+{
+    if (T < 1 || N < 1 || H < 1 || ld < N) return -1;
+    for (int k = 1; k <= H; k++)
+        for (int64_t r = 0; r < T; r++)
+            for (int64_t j = 0; j < N; j++) {
+                double v = 0.0;
+                for (int m = 1; m <= k; m++) {
+                    double x = fop[frac_row(r, m, k, T) * ld + fdiv((int64_t)m * j, k)];
+                    v = (m == 1) ? x : v + x;
+                }
+                hp[((int64_t)(k - 1) * T + r) * N + j] = v;
+            }
+    return 0;
+}
+
+/* Detection on the fractional planes: the same test, word and order as
+ * hso_detect_f32 (plane k, then row, then bin). */
+int hso_detect_frac_f32(const float* fop, int64_t T, int64_t N, int64_t ld, int H,
+                        const float* ta, float scale, uint32_t* idx, float* pw,
+                        int64_t cap, int64_t* counts)
+{
+    if (T < 1 || N < 1 || H < 1 || ld < N || !(scale > 0.0f)) return -1;
+    int s_row, s_k, s_bin;
+    if (hso_field_bits(T, N, H, &s_row, &s_k, &s_bin) != 0) return -2;
+    int64_t o = 0;
+    for (int k = 1; k <= H; k++) {
+        int64_t n_k = 0;
+        for (int64_t r = 0; r < T; r++) {
+            float thr = ta[(int64_t)(k - 1) * T + r] * scale;
+            uint32_t hi = (uint32_t)(((uint64_t)r << (s_k + s_bin)) | ((uint64_t)(k - 1) << s_bin));
+            for (int64_t j = 0; j < N; j++) {
+                float v = frac_point_f32(fop, ld, T, r, j, k);
+                if (v > thr) {
+                    if (o < cap) { idx[o] = hi | (uint32_t)j; pw[o] = v / scale; }
+                    o++;
+                    n_k++;
+                }
+            }
+        }
+        counts[k - 1] = n_k;
+    }
+    counts[H] = o;
+    return o > cap ? -3 : 0;
 }

@@ -42,6 +42,19 @@ MUTANTS = {
     # transpose misses the largest stretch factor
     "vjp_dropped_term": ("for (int m = 1; m <= k; m++)\n                    dfop",
                          "for (int m = 1; m < k; m++)\n                    dfop"),
+    # fractional variant: the point itself (m = k) left out
+    "frac_last_term": ("    for (int m = 1; m <= k; m++) {\n        float x = fop[frac_row",
+                       "    for (int m = 1; m < k; m++) {\n        float x = fop[frac_row"),
+    # fractional variant: floor(i/k) * m instead of floor(m i/k) for rows
+    "frac_row_product": ("    return fdiv(m * (r - c), k) + c;", "    return fdiv(r - c, k) * m + c;"),
+    # fractional variant: m * floor(j/k) instead of floor(m j/k) for bins
+    "frac_bin_product": ("float x = fop[frac_row(r, m, k, T) * ld + fdiv((int64_t)m * j, k)];",
+                         "float x = fop[frac_row(r, m, k, T) * ld + (int64_t)m * fdiv(j, k)];"),
+    # fractional variant: rows not stretched
+    "frac_rows_unstretched": ("    return fdiv(m * (r - c), k) + c;", "    return r + 0 * m * k * c;"),
+    # fractional variant: detection compares the wrong plane's threshold
+    "frac_threshold_plane": ("            float thr = ta[(int64_t)(k - 1) * T + r] * scale;\n            uint32_t hi",
+                             "            float thr = ta[(int64_t)(k > 1 ? k - 2 : 0) * T + r] * scale;\n            uint32_t hi"),
     # fp64 planes summed with a wrong sign
     "f64_sign": ("double sp = fop[rs * ld + fdiv(j, k)];\n                cur[r * N + j] = (k == 1) ? sp : prev[r * N + j] + sp;",
                  "double sp = fop[rs * ld + fdiv(j, k)];\n                cur[r * N + j] = (k == 1) ? sp : prev[r * N + j] - sp;"),
@@ -68,6 +81,11 @@ def _pin_calls():
         pins.test_packing_paper_formula,
         pins.test_vjp_scatter_equals_boxsum,
         pins.test_vjp_adjoint_identity,
+        lambda: pins.test_frac_integer_planes_exact(9, 257, 16),
+        pins.test_frac_k1_identity_and_k2_equals_paper,
+        pins.test_frac_hand_points,
+        lambda: pins.test_frac_harmonic_sum_closed_form(-1),
+        pins.test_frac_detect_matches_thresholded_planes,
     ]
 
 

@@ -435,3 +435,124 @@ def test_select_top_against_sorted_brute_force():
             assert [int(x) for x in oi[kk - 1, :len(want)]] == [w for w, _ in want]
             got_bits = op[kk - 1, :len(want)].view(np.uint32).tolist()
             assert got_bits == [int(np.float32(p).view(np.uint32)) for _, p in want]
+
+
+# --- fractional variant: HPF_k(i,j) = sum_{m=1..k} FOP(floor(m i/k), floor(m j/k)) ---
+# (the incoherent-sum reading of "the FOP at the fractions m/k of each point";
+# not Eq. 1-2 of the paper, which it matches only for k <= 2)
+
+@pytest.mark.parametrize("T,N,H", [(5, 64, 8), (9, 257, 16), (21, 1000, 8), (64, 300, 8)])
+def test_frac_integer_planes_exact(T, N, H):
+    """Integer-valued FOP: the fp32 and fp64 oracles equal whole-plane integer
+    gather-sums (numpy, no rounding) bit for bit."""
+    rng = np.random.default_rng(T * 7 + N)
+    x = rng.integers(0, 16, size=(T, N))
+    ref = brute.frac_planes_int(x, H)
+    assert np.array_equal(oracle.sum_frac_f32(x.astype(np.float32), H).astype(np.int64), ref)
+    assert np.array_equal(oracle.sum_frac_f64(x.astype(np.float64), H).astype(np.int64), ref)
+
+
+def test_frac_k1_identity_and_k2_equals_paper():
+    """HPF_1 is the FOP; HPF_2 adds the same two points as Eq. 2's HP_2 (two
+    fp32 terms commute, so bitwise); from k = 3 on the mappings differ."""
+    fop = rand_exp(21, 700, 5)
+    hf = oracle.sum_frac_f32(fop, 8)
+    hp = oracle.sum_f32(fop, 8)
+    assert np.array_equal(hf[0], fop)
+    assert np.array_equal(hf[1].view(np.uint32), hp[1].view(np.uint32))
+    assert not np.array_equal(hf[2], hp[2])
+
+
+# Spike plane for the hand-derived values: T = 9 (row centre c = 4, storage
+# row r holds i = r - 4), value 1 at (r = 3, i.e. i = -1; bin 5) and 2 at
+# (r = 4, i = 0; bin 6).  Each entry: (k, r, j, value), value = the sum of the
+# spikes hit by the points (floor(m i/k), floor(m j/k)), m = 1..k.
+FRAC_HAND = [
+    (2, 3, 10, 1.0),   # m=1: (floor(-1/2), floor(10/2)) = (-1, 5)
+    (2, 3, 11, 1.0),   # m=1: (-1, 5); m=2: (-1, 11)
+    (2, 2, 10, 1.0),   # i=-2, m=1: (-1, 5)
+    (2, 4, 10, 0.0),   # i=0: (0, 5), (0, 10)
+    (2, 4, 12, 2.0),   # m=1: (0, 6)
+    (3, 3, 15, 1.0),   # m=1: (floor(-1/3), floor(15/3)) = (-1, 5)
+    (3, 3, 8, 1.0),    # m=2: (floor(-2/3), floor(16/3)) = (-1, 5)
+    (3, 2, 8, 0.0),    # i=-2: (-1, 2), (-2, 5), (-2, 8)
+    (4, 3, 20, 1.0),   # m=1: (-1, 5)
+    (4, 3, 7, 1.0),    # m=3: (floor(-3/4), floor(21/4)) = (-1, 5)
+    (4, 3, 10, 1.0),   # m=2: (floor(-2/4), floor(20/4)) = (-1, 5)
+    (5, 3, 10, 0.0),   # i=-1: (-1, 2), (-1, 4), (-1, 6), (-1, 8), (-1, 10)
+    (3, 4, 9, 2.0),    # i=0, m=2: (0, 6)
+]
+
+
+def test_frac_hand_points():
+    """Values derived by hand at single points of a two-spike plane, with
+    negative template indices (floor, not truncation)."""
+    fop = np.zeros((9, 32), dtype=np.float32)
+    fop[3, 5] = 1.0
+    fop[4, 6] = 2.0
+    hf = oracle.sum_frac_f32(fop, 6)
+    for k, r, j, v in FRAC_HAND:
+        assert hf[k - 1, r, j] == v, (k, r, j)
+    # (k=6, r=3, j=12): the six points are (-1, 2), (-1, 4), (-1, 6), (-1, 8),
+    # (-1, 10), (-1, 12): none is a spike (bin 6 holds its spike at i = 0)
+    assert hf[5, 3, 12] == 0.0
+
+
+@pytest.mark.parametrize("z0", [-1, 0, 1])
+def test_frac_harmonic_sum_closed_form(z0):
+    """Noise-free plane with 20/n at (n z0, n f0): at (k z0, k f0) the k
+    fractions m/k land exactly on the harmonics m = 1..k, so HPF_k there is
+    20 (1 + 1/2 + ... + 1/k); Eq. 2's HP_k there is 20 sigma(k)/k instead."""
+    T, N, H, f0 = 21, 4096, 8, 97
+    fop = np.zeros((T, N), dtype=np.float32)
+    synth.inject(fop, [(z0, f0, 20.0, 8)])
+    hf = oracle.sum_frac_f32(fop, H).astype(np.float64)
+    hd = oracle.sum_frac_f64(fop, H)
+    c = T // 2
+    expect = [20.0, 30.0, 110.0 / 3, 125.0 / 3, 137.0 / 3, 49.0, 363.0 / 7, 761.0 / 14]
+    for k in range(1, H + 1):
+        # the injected 20/n are fp32 values (relative error <= 2^-24 each)
+        assert hd[k - 1, k * z0 + c, k * f0] == pytest.approx(expect[k - 1], rel=1e-7)
+        assert hf[k - 1, k * z0 + c, k * f0] == pytest.approx(expect[k - 1], rel=1e-6)
+
+
+def test_frac_point_definition():
+    """Single points of an Exp(1) plane against a plain loop in Python floats."""
+    fop = rand_exp(21, 512, 13)
+    hd = oracle.sum_frac_f64(fop, 8)
+    rows = fop.astype(np.float64).tolist()
+    for (k, r, j) in [(1, 0, 0), (3, 0, 511), (8, 20, 500), (5, 7, 333), (7, 10, 1), (8, 3, 77)]:
+        assert hd[k - 1, r, j] == pytest.approx(brute.frac_point_py(rows, k, r, j), rel=1e-13)
+
+
+@pytest.mark.parametrize("T,N,H", [(5, 64, 8), (21, 1024, 8), (9, 333, 16)])
+def test_frac_f32_within_summation_bound(T, N, H):
+    """fp32 sums of k non-negative terms lie within (k-1) 2^-24 S of fp64."""
+    fop = rand_exp(T, N, 17)
+    hf = oracle.sum_frac_f32(fop, H).astype(np.float64)
+    hd = oracle.sum_frac_f64(fop, H)
+    for k in range(1, H + 1):
+        assert np.all(np.abs(hf[k - 1] - hd[k - 1]) <= (k - 1) * 2.0 ** -24 * hd[k - 1] * (1 + 1e-6))
+
+
+def test_frac_detect_matches_thresholded_planes():
+    """Detection on the fractional planes: the candidates of thresholding the
+    fp32 planes, with the Sec. III word, in (k, row, bin) order; exact counts
+    also past a small capacity, and a power-of-two input scale."""
+    T, N, H = 21, 3000, 8
+    fop = rand_exp(T, N, 19)
+    ta = np.stack([np.full(T, k + 2.5 * math.sqrt(k), np.float32) for k in range(1, H + 1)])
+    ta[2, 5] = -np.inf
+    hf = oracle.sum_frac_f32(fop, H)
+    k, r, j, p = brute.candidates_from_planes(hf, ta)
+    idx, pw, cnt = oracle.detect_frac_f32(fop, H, ta)
+    want = np.array([oracle.pack(rr, kk, jj, N, H) for kk, rr, jj in zip(k, r, j)], dtype=np.uint32)
+    assert np.array_equal(idx, want)
+    assert np.array_equal(pw.view(np.uint32), p.astype(np.float32).view(np.uint32))
+    assert list(cnt[:H]) == [int((k == kk).sum()) for kk in range(1, H + 1)] and cnt[H] == len(want)
+    i2, p2, c2 = oracle.detect_frac_f32(fop, H, ta, cap=10)
+    assert np.array_equal(c2, cnt) and np.array_equal(i2, want[:10])
+    s = 0.125
+    i3, p3, c3 = oracle.detect_frac_f32(fop * s, H, ta, scale=s)
+    assert np.array_equal(c3, cnt) and np.array_equal(i3, want)
+    assert np.array_equal(p3.view(np.uint32), pw.view(np.uint32))
