@@ -230,11 +230,11 @@ def diff_leg(n_fops, steps, warmup, dev):
 
     def fwd():
         for f, x in enumerate(fops):
-            hs.hs_lse_forward(plan.handle, x, x.stride(0), tau, lse[f], work)
+            hs.hs_lse_forward(plan.handle, x, x.stride(0), tau, lse[f], None, work)
 
     def bwd():
         for f, x in enumerate(fops):
-            hs.hs_lse_backward(plan.handle, x, x.stride(0), lse[f], tau, 1.0, dfop, work)
+            hs.hs_lse_backward(plan.handle, x, x.stride(0), lse[f], tau, None, dfop, work)
 
     out = {}
     for name, fn in (("forward", fwd), ("backward", bwd)):

@@ -58,6 +58,16 @@ typedef enum hs_status {
     HS_ERR_NOMEM = -5         /* host or device allocation failed             */
 } hs_status;
 
+/* Which points a harmonic plane sums (Sec. III). */
+typedef enum hs_mapping {
+    HS_MAP_PAPER = 0,         /* Eq. 1-2: HP_k = sum_{m=1..k} FOP(floor(i/m),  */
+                              /* floor(j/m)), cumulative over k (default)      */
+    HS_MAP_FRACTIONAL = 1     /* HP_k = sum_{m=1..k} FOP(floor(m i/k),         */
+                              /* floor(m j/k)): the FOP at the fractions m/k   */
+                              /* of each point, terms added in m order; not    */
+                              /* cumulative.  hs_sum and hs_detect only.       */
+} hs_mapping;
+
 typedef enum hs_dtype {
     HS_DTYPE_F32 = 0,         /* IEEE binary32 power                          */
     HS_DTYPE_F16 = 1,         /* IEEE binary16 of power * input_scale         */
@@ -95,6 +105,7 @@ typedef struct hs_plan_desc {
                                /* walk needs N_temp >= 2 and a threshold table   */
                                /* of at most 16 KB; otherwise the tile kernel    */
                                /* runs.  Results do not depend on it.            */
+    int32_t mapping;           /* hs_mapping (0 = HS_MAP_PAPER)                  */
 } hs_plan_desc;
 
 /* Geometry chosen by the planner (host values; no GPU needed). */
@@ -111,12 +122,14 @@ typedef struct hs_plan_info {
     int32_t src_rows[17];       /* src_rows[m]: distinct source rows of stretch  */
                                 /* factor m over one full-height tile            */
     int64_t staged_words;       /* source words staged per full tile, m >= 2     */
-    int32_t detector;           /* detection kernel: 1 strip walk, 0 tile kernel */
+    int32_t detector;           /* detection kernel: 0 tile kernel, 1 strip      */
+                                /* walk, 2 fractional-mapping kernel             */
+    int32_t mapping;            /* hs_mapping of the plan                        */
 } hs_plan_info;
 
 /* Create a plan.  Validates the shapes (HS_ERR_INVALID: N_temp < 1, n_hp
- * outside 1..16, unknown dtype, input_scale not a power of two, n_fops
- * outside 0..65535,
+ * outside 1..16, unknown dtype or mapping, input_scale not a power of
+ * two, n_fops outside 0..65535, a batch with the fractional mapping,
  * a bin count < 1, or a candidate word wider than 32 bits, i.e.
  * ceil(log2 N_temp) + ceil(log2 N_hp) + ceil(log2 N_chan) > 32).  Host only:
  * touches no GPU. */
@@ -136,23 +149,16 @@ hs_status hs_plan_info_get(const hs_plan* plan, hs_plan_info* info);
  * (0: the plan walks tiles in contiguous chunks), or -1 for a NULL plan. */
 int64_t hs_plan_schedule(const hs_plan* plan, uint32_t* words, int64_t capacity);
 
-/* Copy the plan's device tables (unit schedule and row table of the
- * detection kernel, tile schedule of the other kernels) to the current
- * device, synchronously.  Every call makes this copy itself on first use on
- * a device, except under stream capture: a detection call (hs_detect,
- * hs_detect_batched) being captured on a device that has no copy yet returns
- * HS_ERR_INVALID, so call this (or make one eager call) before capturing a
- * graph.  The copy is freed by hs_plan_destroy.  HS_ERR_NOMEM / HS_ERR_HIP
- * on allocation or copy failure. */
+/* Copy the plan's device tables (unit schedule and row table of the strip
+ * walk, tile schedule of the tile kernels, per-FOP table of a batched plan)
+ * to the current device, synchronously.  Every GPU call of a plan makes this
+ * copy itself on first use on a device, except under stream capture: a call
+ * being captured on a device that has no copy yet returns HS_ERR_INVALID and
+ * launches nothing, so call this (or make one eager call) before capturing a
+ * graph.  Calls also return HS_ERR_INVALID for a stream of another device
+ * than the current one.  The copies are freed by hs_plan_destroy.
+ * HS_ERR_NOMEM / HS_ERR_HIP on allocation or copy failure. */
 hs_status hs_plan_upload(const hs_plan* plan);
-
-/* Single-FOP calls (hs_sum, hs_detect, hs_lse_*): the first such call on a
- * device that is not under stream capture copies the plan's tile schedule
- * (4 bytes per full tile, freed by hs_plan_destroy) to that device; before
- * that copy exists the kernels walk the tiles in contiguous chunks, with
- * the same results, as they do for a stream of another device than the
- * current one.  Make one eager call before capturing a graph to get the
- * scheduled order inside the graph. */
 
 /* All harmonic planes (Eq. 1-2), materialised: hp is [n_hp][N_temp][N_chan]
  * fp32 (plane-major, leading dimension N_chan) in unscaled units.
@@ -199,8 +205,10 @@ hs_status hs_detect_singlehp(const hs_plan* plan, const float* fop, int64_t ld, 
                              hs_cand* out, int64_t capacity, int64_t* counts, void* work, void* stream);
 
 /* hs_detect over a batch of FOPs of different lengths in one launch of a
- * persistent kernel (no host synchronisation and no allocation inside, so
- * the call can be captured into a HIP graph).  All arrays are DEVICE arrays:
+ * persistent kernel.  Once the plan's tables are on the device
+ * (hs_plan_upload or one eager call) the call does no host synchronisation
+ * and no allocation, so it can be captured into a HIP graph; before that a
+ * captured call returns HS_ERR_INVALID.  All arrays are DEVICE arrays:
  *   fops        [n_fops] pointers to the FOPs (each with the plan's dtype)
  *   lds         [n_fops] leading dimensions
  *   ta          [n_hp][N_temp], shared by every FOP
@@ -239,23 +247,27 @@ hs_status hs_sum_backward(const hs_plan* plan, const float* g, float* dfop, void
 
 /* Log-sum-exp statistic of each plane of one FOP (tau > 0):
  *   lse[k-1] = log sum_{i,j} exp(HP_k(i,j) / tau)        ([n_hp] fp64, device)
+ * and, when `loss` is not NULL, the scalar
+ *   *loss = sum_{k=1..n_hp} tau * lse[k-1]               (fp64, device; k order)
  * formed with running maxima and a fixed-order reduction (deterministic for
  * a given device and plan).  For fp32 plans hs_lse_forward is fused: each
  * lane keeps a (maximum, sum of exponentials) pair per plane over the points
  * it forms, the pairs are merged per block and then over the blocks in
  * order, and no plane is stored; other storage types materialise the planes
  * in `work` first.  hs_lse_backward overwrites dfop [N_temp][N_chan] fp32
- * with gscale times the gradient of L = sum_k tau * lse[k-1] with respect to
- * the FOP (unscaled units): the weights exp(HP_k / tau - lse[k-1]) taken
- * through hs_sum_backward; it materialises the weights in `work` (fp32
- * plans form them inside the tile kernel; other storage types store the
- * planes and turn them into weights in a second pass).  `work`
- * must hold hs_lse_workspace_bytes(plan) bytes.  Single-FOP plans only. */
+ * with g times the gradient of L = sum_k tau * lse[k-1] with respect to the
+ * FOP (unscaled units), g = *gscale (fp64, device; NULL means 1), so that an
+ * autograd engine can pass the upstream gradient without a host copy: the
+ * weights exp(HP_k / tau - lse[k-1]) taken through hs_sum_backward; it
+ * materialises the weights in `work` (fp32 plans form them inside the tile
+ * kernel; other storage types store the planes and turn them into weights in
+ * a second pass).  `work` must hold hs_lse_workspace_bytes(plan) bytes.
+ * Single-FOP plans only. */
 size_t hs_lse_workspace_bytes(const hs_plan* plan);
 hs_status hs_lse_forward(const hs_plan* plan, const void* fop, int64_t ld, float tau, double* lse,
-                         void* work, void* stream);
+                         double* loss, void* work, void* stream);
 hs_status hs_lse_backward(const hs_plan* plan, const void* fop, int64_t ld, const double* lse,
-                          float tau, float gscale, float* dfop, void* work, void* stream);
+                          float tau, const double* gscale, float* dfop, void* work, void* stream);
 
 /* Host check of counts copied back from hs_detect: HS_ERR_OVERFLOW when
  * counts[n_hp] > capacity, HS_OK otherwise. */

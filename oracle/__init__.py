@@ -60,7 +60,7 @@ def load_library(path):
     lib.hso_touch_counts.argtypes = [I64, I64, I, ctypes.c_uint32, P]
     lib.hso_sum_frac_f32.argtypes = [P, I64, I64, I64, I, P]
     lib.hso_sum_frac_f64.argtypes = [P, I64, I64, I64, I, P]
-    lib.hso_detect_frac_f32.argtypes = [P, I64, I64, I64, I, P, ctypes.c_float, P, P, I64, P]
+    lib.hso_detect_frac_f32.argtypes = [P, I64, I64, I64, I, P, ctypes.c_float, P, P, I64, P, I]
     lib.hso_pack.argtypes = [I64, I, I64, I64, I]
     lib.hso_pack.restype = ctypes.c_uint32
     lib.hso_field_bits.argtypes = [I64, I64, I, P, P, P]
@@ -163,9 +163,10 @@ def sum_frac_f64(fop, H, n_chan=None):
     return hp
 
 
-def detect_frac_f32(fop, H, ta, scale=1.0, cap=None, n_chan=None):
+def detect_frac_f32(fop, H, ta, scale=1.0, cap=None, n_chan=None, nthreads=1):
     """Candidates of the fractional-variant planes, in (k, row, bin) order,
-    with the word and counts of detect_f32."""
+    with the word and counts of detect_f32 (nthreads: OpenMP threads over
+    rows; the result does not depend on it)."""
     fop = np.ascontiguousarray(fop, dtype=np.float32)
     T, N, ld = _plane_args(fop, n_chan)
     ta = np.ascontiguousarray(ta, dtype=np.float32)
@@ -178,7 +179,7 @@ def detect_frac_f32(fop, H, ta, scale=1.0, cap=None, n_chan=None):
     pw = np.empty(max(cap, 1), dtype=np.float32)
     counts = np.zeros(H + 1, dtype=np.int64)
     rc = _load().hso_detect_frac_f32(_ptr(fop), T, N, ld, H, _ptr(ta), float(scale),
-                                     _ptr(idx), _ptr(pw), cap, _ptr(counts))
+                                     _ptr(idx), _ptr(pw), cap, _ptr(counts), int(nthreads))
     if rc not in (0, -3):
         raise ValueError("hso_detect_frac_f32 rc=%d" % rc)
     n = min(int(counts[H]), cap)

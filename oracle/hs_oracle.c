@@ -296,31 +296,60 @@ int hso_sum_frac_f64(const double* fop, int64_t T, int64_t N, int64_t ld, int H,
 }
 
 /* Detection on the fractional planes: the same test, word and order as
- * hso_detect_f32 (plane k, then row, then bin). */
+ * hso_detect_f32 (plane k, then row, then bin).  Rows are independent: a
+ * first pass counts each row's candidates (OpenMP over rows), the second
+ * forms the values again and writes them at the rows' offsets. */
 int hso_detect_frac_f32(const float* fop, int64_t T, int64_t N, int64_t ld, int H,
                         const float* ta, float scale, uint32_t* idx, float* pw,
-                        int64_t cap, int64_t* counts)
+                        int64_t cap, int64_t* counts, int nthreads)
 {
     if (T < 1 || N < 1 || H < 1 || ld < N || !(scale > 0.0f)) return -1;
     int s_row, s_k, s_bin;
     if (hso_field_bits(T, N, H, &s_row, &s_k, &s_bin) != 0) return -2;
-    int64_t o = 0;
+    int64_t* rowoff = (int64_t*)malloc(sizeof(int64_t) * (size_t)(T * H + 1));
+    if (!rowoff) return -4;
+#ifdef _OPENMP
+    if (nthreads < 1) nthreads = 1;
+#pragma omp parallel for schedule(dynamic, 1) num_threads(nthreads)
+#else
+    (void)nthreads;
+#endif
+    for (int64_t e = 0; e < T * H; e++) {
+        int k = (int)(e / T) + 1;
+        int64_t r = e % T;
+        float thr = ta[(int64_t)(k - 1) * T + r] * scale;
+        int64_t n = 0;
+        for (int64_t j = 0; j < N; j++) n += (frac_point_f32(fop, ld, T, r, j, k) > thr);
+        rowoff[e] = n;
+    }
+    int64_t run = 0;
     for (int k = 1; k <= H; k++) {
-        int64_t n_k = 0;
+        int64_t start = run;
         for (int64_t r = 0; r < T; r++) {
-            float thr = ta[(int64_t)(k - 1) * T + r] * scale;
-            uint32_t hi = (uint32_t)(((uint64_t)r << (s_k + s_bin)) | ((uint64_t)(k - 1) << s_bin));
-            for (int64_t j = 0; j < N; j++) {
-                float v = frac_point_f32(fop, ld, T, r, j, k);
-                if (v > thr) {
-                    if (o < cap) { idx[o] = hi | (uint32_t)j; pw[o] = v / scale; }
-                    o++;
-                    n_k++;
-                }
+            int64_t n = rowoff[(int64_t)(k - 1) * T + r];
+            rowoff[(int64_t)(k - 1) * T + r] = run;
+            run += n;
+        }
+        counts[k - 1] = run - start;
+    }
+    counts[H] = run;
+#ifdef _OPENMP
+#pragma omp parallel for schedule(dynamic, 1) num_threads(nthreads)
+#endif
+    for (int64_t e = 0; e < T * H; e++) {
+        int k = (int)(e / T) + 1;
+        int64_t r = e % T;
+        float thr = ta[(int64_t)(k - 1) * T + r] * scale;
+        uint32_t hi = (uint32_t)(((uint64_t)r << (s_k + s_bin)) | ((uint64_t)(k - 1) << s_bin));
+        int64_t o = rowoff[e];
+        for (int64_t j = 0; j < N; j++) {
+            float v = frac_point_f32(fop, ld, T, r, j, k);
+            if (v > thr) {
+                if (o < cap) { idx[o] = hi | (uint32_t)j; pw[o] = v / scale; }
+                o++;
             }
         }
-        counts[k - 1] = n_k;
     }
-    counts[H] = o;
-    return o > cap ? -3 : 0;
+    free(rowoff);
+    return run > cap ? -3 : 0;
 }

@@ -48,7 +48,7 @@ class hs_plan_desc(ctypes.Structure):
                 ("dtype", ctypes.c_int32), ("input_scale", ctypes.c_float),
                 ("n_fops", ctypes.c_int32), ("n_chans", ctypes.POINTER(ctypes.c_int64)),
                 ("tile_rows", ctypes.c_int32), ("persistent_blocks", ctypes.c_int32),
-                ("schedule", ctypes.c_int32)]
+                ("schedule", ctypes.c_int32), ("mapping", ctypes.c_int32)]
 
 
 class hs_plan_info(ctypes.Structure):
@@ -58,7 +58,8 @@ class hs_plan_info(ctypes.Structure):
                 ("tile_bins", ctypes.c_int32), ("tile_rows", ctypes.c_int32),
                 ("row_blocks", ctypes.c_int32), ("lds_bytes", ctypes.c_int32),
                 ("tiles_total", ctypes.c_int64), ("src_rows", ctypes.c_int32 * 17),
-                ("staged_words", ctypes.c_int64), ("detector", ctypes.c_int32)]
+                ("staged_words", ctypes.c_int64), ("detector", ctypes.c_int32),
+                ("mapping", ctypes.c_int32)]
 
 
 _P = ctypes.c_void_p
@@ -81,8 +82,8 @@ _SIG = {
     "hs_backward_workspace_bytes": ([_P], ctypes.c_size_t),
     "hs_sum_backward": ([_P, _P, _P, _P, _P], ctypes.c_int),
     "hs_lse_workspace_bytes": ([_P], ctypes.c_size_t),
-    "hs_lse_forward": ([_P, _P, _I64, ctypes.c_float, _P, _P, _P], ctypes.c_int),
-    "hs_lse_backward": ([_P, _P, _I64, _P, ctypes.c_float, ctypes.c_float, _P, _P, _P],
+    "hs_lse_forward": ([_P, _P, _I64, ctypes.c_float, _P, _P, _P, _P], ctypes.c_int),
+    "hs_lse_backward": ([_P, _P, _I64, _P, ctypes.c_float, _P, _P, _P, _P],
                         ctypes.c_int),
     "hs_check_counts": ([ctypes.POINTER(ctypes.c_int64), ctypes.c_int32, _I64], ctypes.c_int),
     "hs_status_string": ([ctypes.c_int], ctypes.c_char_p),
@@ -127,8 +128,12 @@ def _need_cuda(*ts):
 
 # --- C names --------------------------------------------------------------------
 
+HS_MAP_PAPER, HS_MAP_FRACTIONAL = 0, 1
+_MAPPINGS = {"paper": HS_MAP_PAPER, "fractional": HS_MAP_FRACTIONAL}
+
+
 def hs_plan_create(n_temp, n_chan=0, n_hp=8, dtype="f32", input_scale=1.0, n_chans=None,
-                   tile_rows=0, persistent_blocks=0, schedule=0):
+                   tile_rows=0, persistent_blocks=0, schedule=0, mapping="paper"):
     """Create a plan (host only).  Returns an opaque handle (ctypes.c_void_p)."""
     d = hs_plan_desc()
     d.n_temp = int(n_temp)
@@ -144,6 +149,7 @@ def hs_plan_create(n_temp, n_chan=0, n_hp=8, dtype="f32", input_scale=1.0, n_cha
     d.tile_rows = int(tile_rows)
     d.persistent_blocks = int(persistent_blocks)
     d.schedule = int(schedule)
+    d.mapping = _MAPPINGS[mapping] if isinstance(mapping, str) else int(mapping)
     h = ctypes.c_void_p()
     _check(_c_hs_plan_create(ctypes.byref(h), ctypes.byref(d)), "hs_plan_create")
     return h
@@ -239,15 +245,16 @@ def hs_lse_workspace_bytes(handle):
     return int(_c_hs_lse_workspace_bytes(handle))
 
 
-def hs_lse_forward(handle, fop, ld, tau, lse, work, stream=None):
-    _need_cuda(fop, lse, work)
-    _check(_c_hs_lse_forward(handle, _ptr(fop), int(ld), float(tau), _ptr(lse), _ptr(work),
+def hs_lse_forward(handle, fop, ld, tau, lse, loss, work, stream=None):
+    _need_cuda(fop, lse, loss, work)
+    _check(_c_hs_lse_forward(handle, _ptr(fop), int(ld), float(tau), _ptr(lse), _ptr(loss), _ptr(work),
                              _stream(stream)), "hs_lse_forward")
 
 
 def hs_lse_backward(handle, fop, ld, lse, tau, gscale, dfop, work, stream=None):
-    _need_cuda(fop, lse, dfop, work)
-    _check(_c_hs_lse_backward(handle, _ptr(fop), int(ld), _ptr(lse), float(tau), float(gscale),
+    """gscale: a one-element fp64 device tensor (the upstream gradient) or None (1)."""
+    _need_cuda(fop, lse, gscale, dfop, work)
+    _check(_c_hs_lse_backward(handle, _ptr(fop), int(ld), _ptr(lse), float(tau), _ptr(gscale),
                               _ptr(dfop), _ptr(work), _stream(stream)), "hs_lse_backward")
 
 
@@ -266,11 +273,36 @@ def hs_version():
 
 # --- conveniences ------------------------------------------------------------------
 
+def check_tensor(t, what, dtype, shape, device):
+    """ValueError unless t is a contiguous `dtype` tensor of `shape` on
+    `device` (device None: any).  The C ABI takes bare pointers, so shapes of
+    device buffers are checked here, before any launch."""
+    if not isinstance(t, torch.Tensor):
+        raise ValueError("%s must be a tensor" % what)
+    if t.dtype != dtype or tuple(t.shape) != tuple(shape) or not t.is_contiguous():
+        raise ValueError("%s must be a contiguous %s tensor of shape %s (got %s %s)"
+                         % (what, dtype, tuple(shape), t.dtype, tuple(t.shape)))
+    if device is not None and (not t.is_cuda or t.device != device):
+        raise ValueError("%s must be on %s" % (what, device))
+
+
+def check_cand_out(out, capacity, device):
+    """ValueError unless `out` is a contiguous [rows][2] int32 tensor (on
+    `device`, None: any) with at least `capacity` rows."""
+    if not isinstance(out, torch.Tensor) or out.dtype != torch.int32 or out.dim() != 2 \
+            or out.shape[1] != 2 or not out.is_contiguous():
+        raise ValueError("candidate output must be a contiguous [capacity][2] int32 tensor")
+    if capacity < 0 or capacity > out.shape[0]:
+        raise ValueError("capacity %d outside 0..%d (rows of the output)" % (capacity, out.shape[0]))
+    if device is not None and (not out.is_cuda or out.device != device):
+        raise ValueError("candidate output must be on %s" % device)
+
+
 class Plan:
     """Owning wrapper of an hs_plan handle."""
 
     def __init__(self, n_temp, n_chan=0, n_hp=8, dtype="f32", input_scale=1.0, n_chans=None,
-                 tile_rows=0, persistent_blocks=0, schedule=0):
+                 tile_rows=0, persistent_blocks=0, schedule=0, mapping="paper"):
         self.n_temp, self.n_hp = int(n_temp), int(n_hp)
         self.n_chan = int(n_chan or 0)
         self.n_chans = None if n_chans is None else [int(x) for x in n_chans]
@@ -281,7 +313,7 @@ class Plan:
         self.torch_dtype = {0: torch.float32, 1: torch.float16, 2: torch.bfloat16}.get(self.dtype)
         self.input_scale = float(input_scale)
         self.handle = hs_plan_create(n_temp, n_chan, n_hp, self.dtype, input_scale, n_chans,
-                                     tile_rows, persistent_blocks, schedule)
+                                     tile_rows, persistent_blocks, schedule, mapping)
         self.info = hs_plan_info_get(self.handle)
 
     def __del__(self):
@@ -293,19 +325,55 @@ class Plan:
                 pass
             self.handle = None
 
+    # -- argument checks: what the C ABI cannot see (device buffer shapes) ------
+
     def _fop(self, fop):
+        if not isinstance(fop, torch.Tensor) or not fop.is_cuda:
+            raise ValueError("FOP must be a device tensor")
         if fop.dtype != self.torch_dtype or fop.dim() != 2 or fop.shape[0] != self.n_temp:
             raise ValueError("FOP must be [n_temp][ld] of the plan's dtype")
         if fop.stride(1) != 1:
             raise ValueError("FOP rows must be contiguous")
+        if fop.shape[1] < self.n_chan:
+            raise ValueError("FOP has %d bins, the plan %d" % (fop.shape[1], self.n_chan))
         return fop.stride(0)
+
+    @staticmethod
+    def _dev_tensor(t, what, dtype, shape, device):
+        check_tensor(t, what, dtype, shape, device)
+
+    def _ta(self, ta, device):
+        self._dev_tensor(ta, "thresholds", torch.float32, (self.n_hp, self.n_temp), device)
+
+    def _cand_out(self, out, capacity, device):
+        check_cand_out(out, capacity, device)
+
+    def _counts(self, counts, device):
+        self._dev_tensor(counts, "counts", torch.int64, (self.n_hp + 1,), device)
+
+    def _plane(self, t, what, device):
+        self._dev_tensor(t, what, torch.float32, (self.n_temp, self.n_chan), device)
+
+    @staticmethod
+    def _alloc(stream):
+        """Allocate on the stream the call runs on, so that a temporary freed
+        on return is not handed to other work before the kernels are done."""
+        import contextlib
+        return torch.cuda.stream(stream) if stream is not None else contextlib.nullcontext()
+
+    def _work(self, nbytes, device):
+        return torch.empty(max(int(nbytes), 1), dtype=torch.uint8, device=device)
+
+    # -- calls -----------------------------------------------------------------------
 
     def sum(self, fop, out=None, stream=None):
         """All planes [H][T][N] fp32 (unscaled)."""
         ld = self._fop(fop)
         if out is None:
-            out = torch.empty((self.n_hp, self.n_temp, self.n_chan), dtype=torch.float32,
-                              device=fop.device)
+            with self._alloc(stream):
+                out = torch.empty((self.n_hp, self.n_temp, self.n_chan), dtype=torch.float32,
+                                  device=fop.device)
+        self._dev_tensor(out, "planes", torch.float32, (self.n_hp, self.n_temp, self.n_chan), fop.device)
         hs_sum(self.handle, fop, ld, out, stream)
         return out
 
@@ -314,12 +382,17 @@ class Plan:
         out is [capacity][2] int32 (word, power bits), counts [H+1] int64."""
         ld = self._fop(fop)
         dev = fop.device
+        self._ta(ta, dev)
         if capacity is None:
             capacity = out.shape[0] if out is not None else 1 << 20
-        if out is None:
-            out = torch.empty((max(int(capacity), 1), 2), dtype=torch.int32, device=dev)
-        if counts is None:
-            counts = torch.empty(self.n_hp + 1, dtype=torch.int64, device=dev)
+        capacity = int(capacity)
+        with self._alloc(stream):
+            if out is None:
+                out = torch.empty((max(capacity, 1), 2), dtype=torch.int32, device=dev)
+            if counts is None:
+                counts = torch.empty(self.n_hp + 1, dtype=torch.int64, device=dev)
+        self._cand_out(out, capacity, dev)
+        self._counts(counts, dev)
         hs_detect(self.handle, fop, ld, ta, out, capacity, counts, stream)
         return out, counts
 
@@ -327,9 +400,11 @@ class Plan:
         """Per-plane capped lists from the first n rows of a detect output
         ([cap][2] int32): returns ([H][n_cand][2] int32, [H] int64)."""
         dev = cand.device
-        out = torch.zeros((self.n_hp, int(n_cand), 2), dtype=torch.int32, device=dev)
-        cnt = torch.empty(self.n_hp, dtype=torch.int64, device=dev)
-        work = self._work(hs_select_workspace_bytes(self.handle, n), dev)
+        self._cand_out(cand, int(n), dev)
+        with self._alloc(stream):
+            out = torch.zeros((self.n_hp, int(n_cand), 2), dtype=torch.int32, device=dev)
+            cnt = torch.empty(self.n_hp, dtype=torch.int64, device=dev)
+            work = self._work(hs_select_workspace_bytes(self.handle, n), dev)
         hs_select_top(self.handle, cand, n, n_cand, out, cnt, work, stream)
         return out, cnt
 
@@ -338,44 +413,64 @@ class Plan:
         outputs as detect()."""
         ld = self._fop(fop)
         dev = fop.device
+        self._ta(ta, dev)
         if capacity is None:
             capacity = out.shape[0] if out is not None else 1 << 20
-        if out is None:
-            out = torch.empty((max(int(capacity), 1), 2), dtype=torch.int32, device=dev)
-        if counts is None:
-            counts = torch.empty(self.n_hp + 1, dtype=torch.int64, device=dev)
-        work = self._work(hs_singlehp_workspace_bytes(self.handle), dev)
+        capacity = int(capacity)
+        with self._alloc(stream):
+            if out is None:
+                out = torch.empty((max(capacity, 1), 2), dtype=torch.int32, device=dev)
+            if counts is None:
+                counts = torch.empty(self.n_hp + 1, dtype=torch.int64, device=dev)
+            work = self._work(hs_singlehp_workspace_bytes(self.handle), dev)
+        self._cand_out(out, capacity, dev)
+        self._counts(counts, dev)
         hs_detect_singlehp(self.handle, fop, ld, ta, out, capacity, counts, work, stream)
         return out, counts
 
-    def _work(self, nbytes, device):
-        return torch.empty(max(int(nbytes), 1), dtype=torch.uint8, device=device)
-
     def backward(self, g, dfop=None, stream=None):
         """dL/dFOP [T][N] fp32 from g = dL/dHP [H][T][N] fp32 (hs_sum_backward)."""
-        if g.dtype != torch.float32 or tuple(g.shape) != (self.n_hp, self.n_temp, self.n_chan) \
-                or not g.is_contiguous():
-            raise ValueError("g must be a contiguous [n_hp][n_temp][n_chan] fp32 tensor")
-        if dfop is None:
-            dfop = torch.empty((self.n_temp, self.n_chan), dtype=torch.float32, device=g.device)
-        work = self._work(hs_backward_workspace_bytes(self.handle), g.device)
+        if not isinstance(g, torch.Tensor) or not g.is_cuda:
+            raise ValueError("g must be a device tensor")
+        self._dev_tensor(g, "g", torch.float32, (self.n_hp, self.n_temp, self.n_chan), g.device)
+        with self._alloc(stream):
+            if dfop is None:
+                dfop = torch.empty((self.n_temp, self.n_chan), dtype=torch.float32, device=g.device)
+            work = self._work(hs_backward_workspace_bytes(self.handle), g.device)
+        self._plane(dfop, "dfop", g.device)
         hs_sum_backward(self.handle, g, dfop, work, stream)
         return dfop
 
-    def lse(self, fop, tau, stream=None):
-        """[H] fp64 tensor: log sum exp(HP_k / tau) over each plane."""
+    def lse(self, fop, tau, stream=None, with_loss=False):
+        """[H] fp64 tensor: log sum exp(HP_k / tau) over each plane; with
+        with_loss, also the fp64 scalar L = sum_k tau * lse_k (both formed on
+        the device)."""
         ld = self._fop(fop)
-        out = torch.empty(self.n_hp, dtype=torch.float64, device=fop.device)
-        work = self._work(hs_lse_workspace_bytes(self.handle), fop.device)
-        hs_lse_forward(self.handle, fop, ld, tau, out, work, stream)
-        return out
+        with self._alloc(stream):
+            out = torch.empty(self.n_hp, dtype=torch.float64, device=fop.device)
+            loss = torch.empty((), dtype=torch.float64, device=fop.device) if with_loss else None
+            work = self._work(hs_lse_workspace_bytes(self.handle), fop.device)
+        hs_lse_forward(self.handle, fop, ld, tau, out, loss, work, stream)
+        return (out, loss) if with_loss else out
 
-    def lse_backward(self, fop, lse, tau, gscale=1.0, dfop=None, stream=None):
-        """gscale * dL/dFOP for L = sum_k tau * lse_k, [T][N] fp32."""
+    def lse_backward(self, fop, lse, tau, gscale=None, dfop=None, stream=None):
+        """g * dL/dFOP for L = sum_k tau * lse_k, [T][N] fp32.  gscale: None
+        (g = 1), a one-element fp64 device tensor (read by the kernel, no host
+        copy) or a Python number (copied to the device)."""
         ld = self._fop(fop)
-        if dfop is None:
-            dfop = torch.empty((self.n_temp, self.n_chan), dtype=torch.float32, device=fop.device)
-        work = self._work(hs_lse_workspace_bytes(self.handle), fop.device)
+        dev = fop.device
+        self._dev_tensor(lse, "lse", torch.float64, (self.n_hp,), dev)
+        with self._alloc(stream):
+            if isinstance(gscale, (int, float)):
+                gscale = torch.full((), float(gscale), dtype=torch.float64, device=dev)
+            if dfop is None:
+                dfop = torch.empty((self.n_temp, self.n_chan), dtype=torch.float32, device=dev)
+            work = self._work(hs_lse_workspace_bytes(self.handle), dev)
+        if gscale is not None:
+            if not isinstance(gscale, torch.Tensor) or gscale.device != dev or gscale.dtype != torch.float64 \
+                    or gscale.numel() != 1 or not gscale.is_contiguous():
+                raise ValueError("gscale must be a one-element fp64 tensor on %s" % dev)
+        self._plane(dfop, "dfop", dev)
         hs_lse_backward(self.handle, fop, ld, lse, tau, gscale, dfop, work, stream)
         return dfop
 
@@ -408,23 +503,26 @@ class HarmonicSum(torch.autograd.Function):
 
 class HarmonicLSE(torch.autograd.Function):
     """loss = HarmonicLSE.apply(fop, plan, tau): L = sum_k tau * log sum
-    exp(HP_k / tau) over the planes of one fp32 FOP (fp64 scalar).  The
-    backward recomputes the planes and takes the weights through the
-    transpose (hs_lse_backward)."""
+    exp(HP_k / tau) over the planes of one fp32 FOP (fp64 scalar, formed by
+    the library).  The backward recomputes the planes and takes the weights
+    through the transpose (hs_lse_backward), reading the upstream gradient
+    from device memory: no arithmetic here and no host synchronisation."""
 
     @staticmethod
     def forward(ctx, fop, plan, tau):
         if plan.dtype != 0:
             raise ValueError("autograd needs an fp32 plan")
-        lse = plan.lse(fop, tau)
+        lse, loss = plan.lse(fop, tau, with_loss=True)
         ctx.save_for_backward(fop, lse)
         ctx.plan, ctx.tau = plan, float(tau)
-        return (lse * ctx.tau).sum()
+        return loss
 
     @staticmethod
     def backward(ctx, gL):
         fop, lse = ctx.saved_tensors
-        g = float(gL)
+        g = gL.detach()
+        if g.device != fop.device or g.dtype != torch.float64 or not g.is_contiguous():
+            g = g.to(device=fop.device, dtype=torch.float64).contiguous()
         return ctx.plan.lse_backward(fop, lse, ctx.tau, gscale=g), None, None
 
 

@@ -238,34 +238,71 @@ void build_walk(hs_plan* p, bool linear)
     p->walk = true;
 }
 
-// Device copy of the walk tables on the current device.  Made by the first
-// call on a device that is not under stream capture (or by hs_plan_upload);
-// a captured call before that gets HS_ERR_INVALID, since a copy cannot be
-// made inside a graph.
-hs_status device_walk(const hs_plan* p, hipStream_t stream, const unsigned char** out)
+// Device copies of a plan's tables on one device.
+struct DevTabs {
+    const unsigned char* walk = nullptr;   // strip-walk units and row table
+    const uint32_t* sched = nullptr;       // full-tile schedule (null: contiguous chunks)
+    const int64_t* batch = nullptr;        // batched: bins of each FOP, then the tile prefix
+};
+
+hs_status copy_to_device(const void* src, size_t bytes, void** dst)
 {
-    *out = nullptr;
+    void* d = nullptr;
+    if (hipMalloc(&d, bytes) != hipSuccess) return HS_ERR_NOMEM;
+    if (hipMemcpy(d, src, bytes, hipMemcpyHostToDevice) != hipSuccess) {
+        (void)hipFree(d);
+        return HS_ERR_HIP;
+    }
+    *dst = d;
+    return HS_OK;
+}
+
+// Every table the plan has, on the current device: all are copied together
+// (synchronously) by the first call on a device that is not under stream
+// capture, or by hs_plan_upload.  A call under capture on a device that has
+// no copy yet gets HS_ERR_INVALID, since a copy cannot be made inside a
+// graph; so does a stream of another device than the current one (the
+// tables are per device).
+hs_status device_tables(const hs_plan* p, hipStream_t stream, DevTabs* t)
+{
+    *t = DevTabs{};
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return HS_ERR_HIP;
     if (stream) {
-        // the tables are per device: the stream must belong to the current one
         hipDevice_t sd = 0;
         if (hipStreamGetDevice(stream, &sd) != hipSuccess || (int)sd != dev) return HS_ERR_INVALID;
     }
     std::lock_guard<std::mutex> g(p->mu);
-    if (!p->d_walk[dev]) {
+    const bool need_walk = p->walk && !p->d_walk[dev];
+    const bool need_sched = !p->sched.empty() && !p->d_sched[dev];
+    const bool need_batch = p->n_fops > 0 && !p->d_tables[dev];
+    if (need_walk || need_sched || need_batch) {
         hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
         if (hipStreamIsCapturing(stream, &cs) != hipSuccess) return HS_ERR_HIP;
         if (cs != hipStreamCaptureStatusNone) return HS_ERR_INVALID;
-        unsigned char* d = nullptr;
-        if (hipMalloc(&d, p->walk_tab.size()) != hipSuccess) return HS_ERR_NOMEM;
-        if (hipMemcpy(d, p->walk_tab.data(), p->walk_tab.size(), hipMemcpyHostToDevice) != hipSuccess) {
-            (void)hipFree(d);
-            return HS_ERR_HIP;
+        void* d = nullptr;
+        if (need_walk) {
+            const hs_status st = copy_to_device(p->walk_tab.data(), p->walk_tab.size(), &d);
+            if (st != HS_OK) return st;
+            p->d_walk[dev] = static_cast<unsigned char*>(d);
         }
-        p->d_walk[dev] = d;
+        if (need_sched) {
+            const hs_status st = copy_to_device(p->sched.data(), p->sched.size() * sizeof(uint32_t), &d);
+            if (st != HS_OK) return st;
+            p->d_sched[dev] = static_cast<uint32_t*>(d);
+        }
+        if (need_batch) {
+            std::vector<int64_t> h((size_t)p->n_fops * 2 + 1);
+            for (int f = 0; f < p->n_fops; ++f) h[f] = p->n_chans[f];
+            for (int f = 0; f <= p->n_fops; ++f) h[p->n_fops + f] = p->tile_prefix[f];
+            const hs_status st = copy_to_device(h.data(), h.size() * sizeof(int64_t), &d);
+            if (st != HS_OK) return st;
+            p->d_tables[dev] = static_cast<int64_t*>(d);
+        }
     }
-    *out = p->d_walk[dev];
+    t->walk = p->d_walk[dev];
+    t->sched = p->d_sched[dev];
+    t->batch = p->d_tables[dev];
     return HS_OK;
 }
 
@@ -287,38 +324,24 @@ hsk::WalkArgs walk_args(const hs_plan* p, const unsigned char* tab)
     return a;
 }
 
-// Device copy of the plan's schedule on the current device, made by the
-// first call on that device that is not under stream capture; null when the
-// plan has none or no copy exists yet: the kernels then take contiguous
-// chunks, with the same results.
-const uint32_t* device_sched(const hs_plan* p, hipStream_t stream)
+hsk::FracArgs frac_args(const hs_plan* p, const void* fop, int64_t ld)
 {
-    if (p->sched.empty()) return nullptr;
-    int dev = 0;
-    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return nullptr;
-    if (stream) {
-        // a stream of another device: no table (its pointer would be foreign)
-        hipDevice_t sd = 0;
-        if (hipStreamGetDevice(stream, &sd) != hipSuccess || (int)sd != dev) return nullptr;
-    }
-    std::lock_guard<std::mutex> g(p->mu);
-    if (!p->d_sched[dev]) {
-        hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
-        if (hipStreamIsCapturing(stream, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone)
-            return nullptr;
-        uint32_t* d = nullptr;
-        const size_t bytes = p->sched.size() * sizeof(uint32_t);
-        if (hipMalloc(&d, bytes) != hipSuccess) return nullptr;
-        if (hipMemcpy(d, p->sched.data(), bytes, hipMemcpyHostToDevice) != hipSuccess) {
-            (void)hipFree(d);
-            return nullptr;
-        }
-        p->d_sched[dev] = d;
-    }
-    return p->d_sched[dev];
+    hsk::FracArgs a{};
+    a.fop = fop;
+    a.ld = ld;
+    a.T = (int32_t)p->T;
+    a.c = (int32_t)(p->T / 2);
+    a.N = (int32_t)p->N;
+    a.H = p->H;
+    a.scale = p->scale;
+    a.inv_scale = 1.0f / p->scale;
+    a.s_row = p->s_row;
+    a.s_bin = p->s_bin;
+    hsk::frac_magic(a);
+    return a;
 }
 
-hsk::TileArgs tile_args(const hs_plan* p, const void* fop, int64_t ld, hipStream_t stream)
+hsk::TileArgs tile_args(const hs_plan* p, const void* fop, int64_t ld, const DevTabs& t)
 {
     hsk::TileArgs a{};
     a.fop = fop;
@@ -334,7 +357,7 @@ hsk::TileArgs tile_args(const hs_plan* p, const void* fop, int64_t ld, hipStream
     a.s_bin = p->s_bin;
     a.kmask = (1u << p->s_k) - 1u;
     a.table_whole = hsk::table_whole((int)p->T, p->H) ? 1 : 0;
-    a.sched = device_sched(p, stream);
+    a.sched = t.sched;
     return a;
 }
 
@@ -366,8 +389,12 @@ hs_status hs_plan_create(hs_plan** out, const hs_plan_desc* d)
         if (d->n_fops < 0 || d->n_fops > 65535) return HS_ERR_INVALID;
         if (d->tile_rows < 0 || d->persistent_blocks < 0) return HS_ERR_INVALID;
         if (d->schedule < 0 || d->schedule > 4) return HS_ERR_INVALID;
+        if (d->mapping != HS_MAP_PAPER && d->mapping != HS_MAP_FRACTIONAL) return HS_ERR_INVALID;
+        if (d->mapping == HS_MAP_FRACTIONAL && (d->n_fops != 0 || d->n_chan > hsk::kFracMaxBins))
+            return HS_ERR_INVALID;
 
         hs_plan* p = new hs_plan();
+        p->mapping = d->mapping;
         p->T = d->n_temp;
         p->H = d->n_hp;
         p->dtype = d->dtype;
@@ -415,11 +442,12 @@ hs_status hs_plan_create(hs_plan** out, const hs_plan_desc* d)
         // schedule for 0, 2 and 4, contiguous chunks for 1 and 3.
         const bool walk_wins = p->dtype != HS_DTYPE_F32 || p->H > 8;
         const bool want_walk = d->schedule == 1 || d->schedule == 4 || (d->schedule == 0 && walk_wins);
-        if (want_walk && hsk::walk_supported((int)p->T, p->H)) build_walk(p, d->schedule == 1);
+        const bool paper = d->mapping == HS_MAP_PAPER;   // the fractional mapping has a kernel of its own
+        if (paper && want_walk && hsk::walk_supported((int)p->T, p->H)) build_walk(p, d->schedule == 1);
 
         if (d->n_fops == 0) {
             p->tiles_total = p->row_blocks * bin_tiles(p->N);
-            if (d->schedule == 0 || d->schedule == 2 || d->schedule == 4)
+            if (paper && (d->schedule == 0 || d->schedule == 2 || d->schedule == 4))
                 p->sched = build_schedule(p->N / hsk::kTileBins, p->row_blocks);
         } else {
             p->tile_prefix.resize(d->n_fops + 1);
@@ -470,13 +498,8 @@ hs_status hs_plan_upload(const hs_plan* p)
 {
     if (!p) return HS_ERR_INVALID;
     try {
-        if (p->walk) {
-            const unsigned char* tab = nullptr;
-            const hs_status st = device_walk(p, nullptr, &tab);
-            if (st != HS_OK) return st;
-        }
-        (void)device_sched(p, nullptr);
-        return HS_OK;
+        DevTabs t;
+        return device_tables(p, nullptr, &t);
     } catch (...) {
         return HS_ERR_HIP;
     }
@@ -499,7 +522,8 @@ hs_status hs_plan_info_get(const hs_plan* p, hs_plan_info* info)
     info->row_blocks = p->row_blocks;
     info->lds_bytes = p->lds_bytes;
     info->tiles_total = p->tiles_total;
-    info->detector = p->walk ? 1 : 0;
+    info->detector = p->mapping == HS_MAP_FRACTIONAL ? 2 : (p->walk ? 1 : 0);
+    info->mapping = p->mapping;
     // distinct source rows of each stretch factor over the full column, and the
     // words one full-height tile at a 256-bin aligned position stages
     const int64_t c = p->T / 2;
@@ -518,7 +542,15 @@ hs_status hs_sum(const hs_plan* p, const void* fop, int64_t ld, float* hp, void*
     if (!p || !hp || p->n_fops != 0) return HS_ERR_INVALID;
     if (!fop_ok(p, fop, ld, p->N)) return HS_ERR_INVALID;
     try {
-        hsk::TileArgs a = tile_args(p, fop, ld, (hipStream_t)stream);
+        if (p->mapping == HS_MAP_FRACTIONAL) {
+            hsk::FracArgs a = frac_args(p, fop, ld);
+            a.hp = hp;
+            return from_hip(hsk::launch_frac(p->dtype, false, a, (hipStream_t)stream));
+        }
+        DevTabs t;
+        const hs_status st = device_tables(p, (hipStream_t)stream, &t);
+        if (st != HS_OK) return st;
+        hsk::TileArgs a = tile_args(p, fop, ld, t);
         a.hp = hp;
         return from_hip(hsk::launch_fused(hsk::kModeSum, p->dtype, p->H, a, p->tiles_total,
                                           persistent_grid(p, p->tiles_total), p->lds_bytes,
@@ -536,12 +568,20 @@ hs_status hs_detect(const hs_plan* p, const void* fop, int64_t ld, const float* 
     if (!fop_ok(p, fop, ld, p->N)) return HS_ERR_INVALID;
     try {
         hipStream_t s = (hipStream_t)stream;
-        if (p->walk) {
-            const unsigned char* tab = nullptr;
-            const hs_status st = device_walk(p, s, &tab);
-            if (st != HS_OK) return st;
+        DevTabs t;
+        const hs_status st = device_tables(p, s, &t);
+        if (st != HS_OK) return st;
+        if (p->mapping == HS_MAP_FRACTIONAL) {
             if (hsk::launch_zero_i64(counts, p->H + 1, s) != hipSuccess) return HS_ERR_HIP;
-            hsk::WalkArgs a = walk_args(p, tab);
+            hsk::FracArgs a = frac_args(p, fop, ld);
+            a.ta = ta;
+            a.out = out;
+            a.cap = capacity;
+            a.counts = reinterpret_cast<unsigned long long*>(counts);
+            if (hsk::launch_frac(p->dtype, true, a, s) != hipSuccess) return HS_ERR_HIP;
+        } else if (p->walk) {
+            if (hsk::launch_zero_i64(counts, p->H + 1, s) != hipSuccess) return HS_ERR_HIP;
+            hsk::WalkArgs a = walk_args(p, t.walk);
             a.fop = fop;
             a.ld = ld;
             a.N = (int32_t)p->N;
@@ -555,7 +595,7 @@ hs_status hs_detect(const hs_plan* p, const void* fop, int64_t ld, const float* 
         } else {
             hipError_t e = hsk::launch_zero_i64(counts, p->H + 1, s);
             if (e != hipSuccess) return HS_ERR_HIP;
-            hsk::TileArgs a = tile_args(p, fop, ld, s);
+            hsk::TileArgs a = tile_args(p, fop, ld, t);
             a.ta = ta;
             a.out = out;
             a.cap = capacity;
@@ -604,7 +644,7 @@ hs_status hs_detect_singlehp(const hs_plan* p, const float* fop, int64_t ld, con
                              int64_t capacity, int64_t* counts, void* work, void* stream)
 {
     if (!p || p->n_fops != 0 || !ta || !counts || !work || capacity < 0) return HS_ERR_INVALID;
-    if (p->dtype != HS_DTYPE_F32) return HS_ERR_UNSUPPORTED;
+    if (p->dtype != HS_DTYPE_F32 || p->mapping != HS_MAP_PAPER) return HS_ERR_UNSUPPORTED;
     if (capacity > 0 && !out) return HS_ERR_INVALID;
     if (!fop_ok(p, fop, ld, p->N)) return HS_ERR_INVALID;
     try {
@@ -627,12 +667,12 @@ hs_status hs_detect_batched(const hs_plan* p, const void* const* fops, const int
         return HS_ERR_INVALID;
     try {
         hipStream_t s = (hipStream_t)stream;
+        DevTabs t;
+        const hs_status st = device_tables(p, s, &t);
+        if (st != HS_OK) return st;
         if (p->walk) {
-            const unsigned char* tab = nullptr;
-            const hs_status st = device_walk(p, s, &tab);
-            if (st != HS_OK) return st;
             if (hsk::launch_zero_i64(counts, (int64_t)p->n_fops * (p->H + 1), s) != hipSuccess) return HS_ERR_HIP;
-            hsk::WalkArgs a = walk_args(p, tab);
+            hsk::WalkArgs a = walk_args(p, t.walk);
             a.n_fops = p->n_fops;
             a.fops = fops;
             a.lds = lds;
@@ -647,31 +687,7 @@ hs_status hs_detect_batched(const hs_plan* p, const void* const* fops, const int
                                                      reinterpret_cast<unsigned long long*>(counts), p->n_fops,
                                                      p->H, p->s_bin, (1u << p->s_k) - 1u, s));
         }
-        int dev = 0;
-        if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return HS_ERR_HIP;
-        if (stream) {
-            // the plan's tables are per device: the stream must belong to the current one
-            hipDevice_t sd = 0;
-            if (hipStreamGetDevice((hipStream_t)stream, &sd) != hipSuccess || (int)sd != dev) return HS_ERR_INVALID;
-        }
-        int64_t* tables = nullptr;
-        {
-            std::lock_guard<std::mutex> g(p->mu);
-            if (!p->d_tables[dev]) {
-                const size_t n = (size_t)p->n_fops * 2 + 1;
-                std::vector<int64_t> h(n);
-                for (int f = 0; f < p->n_fops; ++f) h[f] = p->n_chans[f];
-                for (int f = 0; f <= p->n_fops; ++f) h[p->n_fops + f] = p->tile_prefix[f];
-                int64_t* d = nullptr;
-                if (hipMalloc(&d, n * sizeof(int64_t)) != hipSuccess) return HS_ERR_NOMEM;
-                if (hipMemcpy(d, h.data(), n * sizeof(int64_t), hipMemcpyHostToDevice) != hipSuccess) {
-                    (void)hipFree(d);
-                    return HS_ERR_HIP;
-                }
-                p->d_tables[dev] = d;
-            }
-            tables = p->d_tables[dev];
-        }
+        const int64_t* tables = t.batch;
         hipError_t e = hsk::launch_zero_i64(counts, (int64_t)p->n_fops * (p->H + 1), s);
         if (e != hipSuccess) return HS_ERR_HIP;
         hsk::BatchArgs b{};
@@ -744,6 +760,7 @@ size_t hs_backward_workspace_bytes(const hs_plan* p)
 hs_status hs_sum_backward(const hs_plan* p, const float* g, float* dfop, void* work, void* stream)
 {
     if (!p || p->n_fops != 0 || !g || !dfop) return HS_ERR_INVALID;
+    if (p->mapping != HS_MAP_PAPER) return HS_ERR_UNSUPPORTED;
     if (partial_bytes(p) > 0 && !work) return HS_ERR_INVALID;
     try {
         return from_hip(hsk::launch_backward(g, dfop, static_cast<float*>(work), (int)p->T, p->N, p->H,
@@ -782,47 +799,58 @@ int lse_grid(const hs_plan* p)
 }  // namespace
 
 hs_status hs_lse_forward(const hs_plan* p, const void* fop, int64_t ld, float tau, double* lse,
-                         void* work, void* stream)
+                         double* loss, void* work, void* stream)
 {
     if (!p || p->n_fops != 0 || !lse || !work || !tau_ok(tau)) return HS_ERR_INVALID;
+    if (p->mapping != HS_MAP_PAPER) return HS_ERR_UNSUPPORTED;
     if (!fop_ok(p, fop, ld, p->N)) return HS_ERR_INVALID;
     try {
         hipStream_t s = (hipStream_t)stream;
+        DevTabs t;
+        const hs_status st = device_tables(p, s, &t);
+        if (st != HS_OK) return st;
         if (p->dtype == HS_DTYPE_F32) {
             // fused: the planes are formed tile by tile and never stored
             const int g = lse_grid(p);
-            hsk::TileArgs a = tile_args(p, fop, ld, s);
+            hsk::TileArgs a = tile_args(p, fop, ld, t);
             a.lse_part = static_cast<float*>(work);
             a.lse_c = (float)(1.4426950408889634 / (double)p->scale / (double)tau);
             hipError_t e = hsk::launch_fused(hsk::kModeLse, p->dtype, p->H, a, p->tiles_total, g,
                                              p->lds_bytes, s);
             if (e != hipSuccess) return HS_ERR_HIP;
-            return from_hip(hsk::launch_lse_fused_final(a.lse_part, g, p->H, 1.0 / (double)p->scale,
-                                                        (double)tau, lse, s));
+            e = hsk::launch_lse_fused_final(a.lse_part, g, p->H, 1.0 / (double)p->scale, (double)tau, lse, s);
+            if (e != hipSuccess) return HS_ERR_HIP;
+            return loss ? from_hip(hsk::launch_lse_loss(lse, p->H, (double)tau, loss, s)) : HS_OK;
         }
         float* planes = static_cast<float*>(work);
         void* tail = static_cast<char*>(work) + round256(plane_bytes(p) * p->H);
-        hsk::TileArgs a = tile_args(p, fop, ld, s);
+        hsk::TileArgs a = tile_args(p, fop, ld, t);
         a.hp = planes;
         hipError_t e = hsk::launch_fused(hsk::kModeSum, p->dtype, p->H, a, p->tiles_total,
                                          persistent_grid(p, p->tiles_total), p->lds_bytes, s);
         if (e != hipSuccess) return HS_ERR_HIP;
-        return from_hip(hsk::launch_lse_reduce(planes, p->T * p->N, p->H, tau, tail, lse, s));
+        e = hsk::launch_lse_reduce(planes, p->T * p->N, p->H, tau, tail, lse, s);
+        if (e != hipSuccess) return HS_ERR_HIP;
+        return loss ? from_hip(hsk::launch_lse_loss(lse, p->H, (double)tau, loss, s)) : HS_OK;
     } catch (...) {
         return HS_ERR_HIP;
     }
 }
 
 hs_status hs_lse_backward(const hs_plan* p, const void* fop, int64_t ld, const double* lse,
-                          float tau, float gscale, float* dfop, void* work, void* stream)
+                          float tau, const double* gscale, float* dfop, void* work, void* stream)
 {
     if (!p || p->n_fops != 0 || !lse || !dfop || !work || !tau_ok(tau)) return HS_ERR_INVALID;
+    if (p->mapping != HS_MAP_PAPER) return HS_ERR_UNSUPPORTED;
     if (!fop_ok(p, fop, ld, p->N)) return HS_ERR_INVALID;
     try {
         hipStream_t s = (hipStream_t)stream;
+        DevTabs t;
+        const hs_status st = device_tables(p, s, &t);
+        if (st != HS_OK) return st;
         float* planes = static_cast<float*>(work);
         float* part = reinterpret_cast<float*>(static_cast<char*>(work) + round256(plane_bytes(p) * p->H));
-        hsk::TileArgs a = tile_args(p, fop, ld, s);
+        hsk::TileArgs a = tile_args(p, fop, ld, t);
         a.hp = planes;
         hipError_t e;
         if (p->dtype == HS_DTYPE_F32) {

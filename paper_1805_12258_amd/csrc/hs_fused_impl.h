@@ -659,8 +659,9 @@ __device__ __forceinline__ void compute_tile(const TileArgs& a, const RowGeo& g,
                 for (int v = 0; v < kV; ++v) o[v] = Scaled<TIn>::value ? acc[v] * a.inv_scale : acc[v];
                 if constexpr (MODE == kModeWeights) {
                     const double lk = a.lse[k - 1];
+                    const float gsc = a.gscale ? (float)*a.gscale : 1.0f;
 #pragma unroll
-                    for (int v = 0; v < kV; ++v) o[v] = a.gscale * expf((float)((double)o[v] * a.inv_tau - lk));
+                    for (int v = 0; v < kV; ++v) o[v] = gsc * expf((float)((double)o[v] * a.inv_tau - lk));
                 }
                 if (FULL && (N & 3) == 0) {
                     *reinterpret_cast<float4*>(dst) = make_float4(o[0], o[1], o[2], o[3]);

@@ -233,6 +233,15 @@ __global__ void k_lse_final(const double* __restrict__ pm, const float* __restri
     lse[k] = M + log((double)S);
 }
 
+// L = sum_k tau * lse[k-1], in k order (fp64).
+__global__ void k_lse_loss(const double* __restrict__ lse, int H, double tau, double* __restrict__ loss)
+{
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    double L = 0.0;
+    for (int k = 0; k < H; ++k) L += tau * lse[k];
+    *loss = L;
+}
+
 // Fused statistic, level 2: one block per plane.  The blocks' pairs (max
 // m_b in storage units, sum s_b of exp((x - m_b) * cd)) are merged in fp64,
 // cd = inv_scale / tau: first the largest m_b, then the sum of
@@ -275,10 +284,13 @@ __global__ __launch_bounds__(kLseFinalThreads) void k_lse_fused_final(const floa
     if (threadIdx.x == 0) lse[k] = M * cd + log(red[0]);
 }
 
-// Weights of L = sum_k tau * lse_k: dL/dHP_k = exp(HP_k / tau - lse_k), times gscale.
+// Weights of L = sum_k tau * lse_k: dL/dHP_k = exp(HP_k / tau - lse_k), times
+// the upstream gradient *gscale (1 when null).
 __global__ __launch_bounds__(256) void k_lse_weights(float* __restrict__ hp, int64_t plane, int H, double inv_tau,
-                                                     const double* __restrict__ lse, float gscale)
+                                                     const double* __restrict__ lse,
+                                                     const double* __restrict__ gscale_p)
 {
+    const float gscale = gscale_p ? (float)*gscale_p : 1.0f;
     const int64_t total = plane * H;
     for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
          e += (int64_t)gridDim.x * blockDim.x) {
@@ -340,7 +352,13 @@ hipError_t launch_lse_fused_final(const float* part, int nblk, int H, double inv
     return hipGetLastError();
 }
 
-hipError_t launch_lse_weights(float* hp, int64_t plane, int H, double tau, const double* lse, float gscale,
+hipError_t launch_lse_loss(const double* lse, int H, double tau, double* loss, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_lse_loss, dim3(1), dim3(64), 0, s, lse, H, tau, loss);
+    return hipGetLastError();
+}
+
+hipError_t launch_lse_weights(float* hp, int64_t plane, int H, double tau, const double* lse, const double* gscale,
                               hipStream_t s)
 {
     hipLaunchKernelGGL(k_lse_weights, dim3(grid_for(plane * H, 256, 65536)), dim3(256), 0, s, hp, plane, H,

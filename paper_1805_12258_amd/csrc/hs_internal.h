@@ -203,7 +203,7 @@ struct TileArgs {
     // gscale * exp(HP_k / tau - lse[k-1])
     const double* lse;      // [H] device
     double inv_tau;
-    float gscale;
+    const double* gscale;         // upstream gradient (device, null: 1)
 };
 
 // Arguments of the batched persistent launch.
@@ -273,6 +273,25 @@ hipError_t launch_fused(int mode, int dtype, int H, const TileArgs& a, int64_t n
 hipError_t launch_batched(int dtype, int H, const BatchArgs& a, int grid, int lds_bytes,
                           hipStream_t s);
 hipError_t launch_zero_i64(int64_t* p, int64_t n, hipStream_t s);
+
+// Fractional mapping (HP_k = sum_{m<=k} FOP(floor(m i/k), floor(m j/k))):
+// planes (hp) or detection (ta, out, cap, counts), single FOP, N <= 2^24.
+constexpr int64_t kFracMaxBins = (int64_t)1 << 24;
+struct FracArgs {
+    const void* fop;
+    int64_t ld;
+    int32_t T, c, N, H;
+    float scale, inv_scale;
+    const float* ta;
+    float* hp;
+    hs_cand* out;
+    int64_t cap;
+    unsigned long long* counts;
+    int32_t s_row, s_bin;
+    uint64_t magic[kMaxH + 1];    // ceil(2^32 / k): floor division by k
+};
+void frac_magic(FracArgs& a);
+hipError_t launch_frac(int dtype, bool detect, const FracArgs& a, hipStream_t s);
 // Per-plane counts of stored candidates (after a detection kernel): lists at
 // out + out_offsets[f] with capacities caps[f] (or one list of capacity `cap`
 // when both are null), counts [n_lists][H+1].
@@ -297,7 +316,8 @@ hipError_t launch_lse_reduce(const float* hp, int64_t plane, int H, double tau, 
                              hipStream_t s);
 hipError_t launch_lse_fused_final(const float* part, int nblk, int H, double inv_scale, double tau,
                                   double* lse, hipStream_t s);
-hipError_t launch_lse_weights(float* hp, int64_t plane, int H, double tau, const double* lse, float gscale,
+hipError_t launch_lse_loss(const double* lse, int H, double tau, double* loss, hipStream_t s);
+hipError_t launch_lse_weights(float* hp, int64_t plane, int H, double tau, const double* lse, const double* gscale,
                               hipStream_t s);
 
 // Canonical candidate order (hs_sort.hip).
@@ -313,6 +333,7 @@ struct hs_plan {
     int dtype = 0;
     float scale = 1.0f;
     int n_fops = 0;
+    int mapping = HS_MAP_PAPER;
     std::vector<int64_t> n_chans;
     int s_row = 0, s_k = 0, s_bin = 0;
     int tile_rows = 0, row_blocks = 0;

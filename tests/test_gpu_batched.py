@@ -122,3 +122,70 @@ def test_batched_graph_replay():
             assert np.array_equal(triples(gi, gp, plan.info["s_row"], plan.info["s_bin"]),
                                   ref[f][0]), (rep, f)
         del junk
+
+
+def _capture_status(fn):
+    """Run fn under stream capture; the library's status (0 when it returned)."""
+    s = torch.cuda.Stream()
+    g = torch.cuda.CUDAGraph()
+    torch.cuda.synchronize()
+    status = 0
+    with torch.cuda.graph(g, stream=s):
+        try:
+            fn(s)
+        except hs.HsError as e:
+            status = e.status
+    torch.cuda.synchronize()
+    return status, g
+
+
+def test_capture_on_fresh_plan_is_rejected():
+    """A captured call on a plan whose tables are not on the device yet gets
+    HS_ERR_INVALID and launches nothing (a copy cannot be made inside a
+    graph), for the batched, walk and tile paths; after hs_plan_upload the
+    same calls capture, and every replay equals the eager result."""
+    H, T = 8, 21
+    lens = [5000, 777, 65536]
+    devs, _ = make_batch(lens, T, H, 8400)
+    ta = synth.thresholds(H, T)
+    caps = [20000] * len(lens)
+    # batched
+    plan = hs.Plan(T, 0, H, n_chans=lens)
+    fops = torch.tensor([d.data_ptr() for d in devs], dtype=torch.int64, device="cuda")
+    lds = torch.tensor([d.stride(0) for d in devs], dtype=torch.int64, device="cuda")
+    offs = torch.tensor(np.concatenate([[0], np.cumsum(caps)[:-1]]), dtype=torch.int64, device="cuda")
+    capd = torch.tensor(caps, dtype=torch.int64, device="cuda")
+    tat = torch.from_numpy(ta).cuda()
+    out = torch.zeros((sum(caps), 2), dtype=torch.int32, device="cuda")
+    counts = torch.zeros((len(lens), H + 1), dtype=torch.int64, device="cuda")
+    call = lambda s: hs.hs_detect_batched(plan.handle, fops, lds, tat, out, offs, capd, counts, stream=s)  # noqa
+    st, _ = _capture_status(call)
+    assert st == hs.HS_ERR_INVALID
+    assert int(counts.abs().sum()) == 0                       # nothing ran
+    hs.hs_plan_upload(plan.handle)
+    st, g = _capture_status(call)
+    assert st == 0
+    g.replay()
+    torch.cuda.synchronize()
+    got = counts.clone()
+    (_, _, _, _, _, _, ref), _ = batched_call(plan, devs, ta, caps)
+    assert torch.equal(got, ref)
+    # single FOP: the tile kernel (fp32, 8 planes) and the strip walk (16 planes)
+    x = devs[2]
+    for Hs in (8, 16):
+        p1 = hs.Plan(T, lens[2], Hs)
+        t1 = torch.from_numpy(synth.thresholds(Hs, T)).cuda()
+        o1 = torch.zeros((1 << 16, 2), dtype=torch.int32, device="cuda")
+        c1 = torch.zeros(Hs + 1, dtype=torch.int64, device="cuda")
+        call1 = lambda s: hs.hs_detect(p1.handle, x, x.stride(0), t1, o1, 1 << 16, c1, stream=s)  # noqa
+        st, _ = _capture_status(call1)
+        assert st == hs.HS_ERR_INVALID, Hs
+        hs.hs_plan_upload(p1.handle)
+        st, g1 = _capture_status(call1)
+        assert st == 0
+        eo, ec = p1.detect(x, t1, capacity=1 << 16)
+        for _ in range(3):
+            c1.fill_(-1)
+            g1.replay()
+            torch.cuda.synchronize()
+            assert torch.equal(c1, ec)

@@ -131,9 +131,13 @@ def test_autograd_wrappers():
     # HarmonicLSE: loss value and gradient equal the direct calls
     xb = x.clone().requires_grad_(True)
     loss = hs.HarmonicLSE.apply(xb, plan, tau)
+    assert loss.is_cuda and loss.dtype == torch.float64 and loss.dim() == 0
     (2.0 * loss).backward()
-    lse = plan.lse(x, tau)
-    assert float(loss.detach()) == pytest.approx(float(tau * lse.sum()), rel=1e-12)
+    lse, L = plan.lse(x, tau, with_loss=True)
+    assert torch.equal(loss.detach(), L)                     # the library's scalar
+    assert float(L) == pytest.approx(float(tau * lse.sum()), rel=1e-12)
+    g2 = torch.full((), 2.0, dtype=torch.float64, device="cuda")
+    assert torch.equal(xb.grad, plan.lse_backward(x, lse, tau, gscale=g2))
     assert torch.equal(xb.grad, plan.lse_backward(x, lse, tau, gscale=2.0))
     S = oracle.sum_f32(x.cpu().numpy(), H)
     assert float(loss.detach()) == pytest.approx(olse.loss_f64(S, tau), abs=H * tau * 1e-5)

@@ -292,3 +292,56 @@ def test_detect_on_side_stream():
     a = out[:n].cpu().numpy()
     got = (a[:, 0].view(np.uint32).copy(), a[:, 1].view(np.float32).copy(), counts)
     assert_same_candidates(got, oracle_detect_sorted(store, H, ta))
+
+
+def test_calls_on_a_stream_that_is_not_current():
+    """stream=s without making s current: the wrappers allocate their
+    temporaries on s, so work queued meanwhile on the current stream cannot
+    reuse them while the kernels on s still run; the results equal the
+    calls on the current stream."""
+    T, N, H, tau = 21, 256 * 64, 8, 0.5
+    x = exp_plane(T, N, 61)
+    ta = random_thresholds(H, T, 62)
+    dev, store = padded_device(x)
+    plan = hs.Plan(T, N, H)
+    t = torch.from_numpy(np.ascontiguousarray(ta, dtype=np.float32)).cuda()
+    ref_out, ref_cnt = plan.detect(dev, t, capacity=H * T * N)
+    lse = plan.lse(dev, tau)
+    ref_g = plan.lse_backward(dev, lse, tau, gscale=0.5)
+    torch.cuda.synchronize()
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    out, cnt = plan.detect(dev, t, capacity=H * T * N, stream=s)
+    g = plan.lse_backward(dev, lse, tau, gscale=0.5, stream=s)
+    junk = [torch.randn(1 << 22, device="cuda") for _ in range(4)]   # current-stream work meanwhile
+    s.synchronize()
+    assert torch.equal(cnt, ref_cnt)
+    n = int(cnt[-1])
+    a = np.sort(out[:n, 0].cpu().numpy().view(np.uint32))
+    b = np.sort(ref_out[:n, 0].cpu().numpy().view(np.uint32))
+    assert np.array_equal(a, b)
+    assert torch.equal(g, ref_g)
+    del junk
+
+
+def test_wrappers_reject_bad_device_buffers():
+    """Bad shapes, dtypes, capacities and short FOP views raise ValueError
+    before any launch."""
+    T, N, H = 9, 1000, 4
+    plan = hs.Plan(T, N, H)
+    x = exp_plane(T, N, 3).cuda()
+    ta = torch.zeros((H, T), device="cuda")
+    with pytest.raises(ValueError):
+        plan.detect(x, ta.double(), capacity=8)
+    with pytest.raises(ValueError):
+        plan.detect(x, ta[0], capacity=8)
+    with pytest.raises(ValueError):
+        plan.detect(x, ta, capacity=100, out=torch.zeros((50, 2), dtype=torch.int32, device="cuda"))
+    with pytest.raises(ValueError):
+        plan.detect(x[:, :N - 1], ta, capacity=8)
+    with pytest.raises(ValueError):
+        plan.sum(x, out=torch.zeros((H, T, N - 1), device="cuda"))
+    with pytest.raises(ValueError):
+        plan.backward(torch.zeros((H, T, N), device="cuda"), dfop=torch.zeros((T, N), dtype=torch.float64, device="cuda"))
+    with pytest.raises(ValueError):
+        plan.lse_backward(x, torch.zeros(H, dtype=torch.float32, device="cuda"), 0.5)

@@ -211,3 +211,51 @@ def test_autotune_search_and_cache(tmp_path):
     at.store_cache(path, key, {"config": best, "ms": ms})
     assert at.load_cache(path)[key]["config"] == best
     assert at.load_cache(str(tmp_path / "missing.json")) == {}
+
+
+def test_mapping_field():
+    """The mapping field: the paper's Eq. 1-2 by default, the fractional
+    variant on request (single FOP, N <= 2^24), anything else rejected."""
+    p = hs.Plan(85, 1 << 21, 8)
+    assert p.info["mapping"] == hs.HS_MAP_PAPER
+    f = hs.Plan(85, 1 << 21, 8, mapping="fractional")
+    assert f.info["mapping"] == hs.HS_MAP_FRACTIONAL and f.info["detector"] == 2
+    assert hs.hs_plan_schedule(f.handle) == []            # no tile schedule of its own
+    for bad in (dict(mapping=2), dict(mapping=-1),
+                dict(mapping="fractional", n_chan=0, n_chans=[100, 200]),
+                dict(mapping="fractional", n_chan=(1 << 24) + 1)):
+        kw = dict(n_temp=9, n_chan=1000, n_hp=8)
+        kw.update(bad)
+        with pytest.raises(hs.HsError) as e:
+            hs.Plan(**kw)
+        assert e.value.status == hs.HS_ERR_INVALID
+
+
+def test_wrapper_argument_checks():
+    """Shapes, dtypes and contiguity of device buffers are checked in Python
+    before any call (the C ABI sees bare pointers); device None skips the
+    device check so that the rules run here without a GPU."""
+    import torch
+    ok = torch.zeros((8, 85), dtype=torch.float32)
+    hs.check_tensor(ok, "ta", torch.float32, (8, 85), None)
+    for bad in (torch.zeros((8, 85), dtype=torch.float64), torch.zeros((85,), dtype=torch.float32),
+                torch.zeros((85, 8), dtype=torch.float32).t(), torch.zeros((8, 84), dtype=torch.float32),
+                [[0.0] * 85] * 8):
+        with pytest.raises(ValueError):
+            hs.check_tensor(bad, "ta", torch.float32, (8, 85), None)
+    with pytest.raises(ValueError):
+        hs.check_tensor(ok, "ta", torch.float32, (8, 85), torch.device("cuda", 0))   # not on the device
+    out = torch.zeros((100, 2), dtype=torch.int32)
+    hs.check_cand_out(out, 100, None)
+    hs.check_cand_out(out, 0, None)
+    for bad, cap in ((out, 101), (out, -1), (torch.zeros((100, 2), dtype=torch.int64), 10),
+                     (torch.zeros((100, 3), dtype=torch.int32), 10), (torch.zeros((2, 100), dtype=torch.int32).t(), 10),
+                     (torch.zeros(200, dtype=torch.int32), 10)):
+        with pytest.raises(ValueError):
+            hs.check_cand_out(bad, cap, None)
+    # Plan methods refuse host tensors and short FOP views before any call
+    plan = hs.Plan(9, 1000, 4)
+    with pytest.raises(ValueError):
+        plan.detect(torch.zeros((9, 1000)), torch.zeros((4, 9)), capacity=8)
+    with pytest.raises(ValueError):
+        plan.sum(torch.zeros((9, 1000)))

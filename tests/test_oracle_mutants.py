@@ -53,8 +53,8 @@ MUTANTS = {
     # fractional variant: rows not stretched
     "frac_rows_unstretched": ("    return fdiv(m * (r - c), k) + c;", "    return r + 0 * m * k * c;"),
     # fractional variant: detection compares the wrong plane's threshold
-    "frac_threshold_plane": ("            float thr = ta[(int64_t)(k - 1) * T + r] * scale;\n            uint32_t hi",
-                             "            float thr = ta[(int64_t)(k > 1 ? k - 2 : 0) * T + r] * scale;\n            uint32_t hi"),
+    "frac_threshold_plane": ("        float thr = ta[(int64_t)(k - 1) * T + r] * scale;\n        int64_t n = 0;\n        for (int64_t j = 0; j < N; j++) n += (frac_point_f32",
+                             "        float thr = ta[(int64_t)(k > 1 ? k - 2 : 0) * T + r] * scale;\n        int64_t n = 0;\n        for (int64_t j = 0; j < N; j++) n += (frac_point_f32"),
     # fp64 planes summed with a wrong sign
     "f64_sign": ("double sp = fop[rs * ld + fdiv(j, k)];\n                cur[r * N + j] = (k == 1) ? sp : prev[r * N + j] + sp;",
                  "double sp = fop[rs * ld + fdiv(j, k)];\n                cur[r * N + j] = (k == 1) ? sp : prev[r * N + j] - sp;"),

@@ -556,3 +556,5 @@ def test_frac_detect_matches_thresholded_planes():
     i3, p3, c3 = oracle.detect_frac_f32(fop * s, H, ta, scale=s)
     assert np.array_equal(c3, cnt) and np.array_equal(i3, want)
     assert np.array_equal(p3.view(np.uint32), pw.view(np.uint32))
+    i4, p4, c4 = oracle.detect_frac_f32(fop, H, ta, nthreads=4)
+    assert np.array_equal(c4, cnt) and np.array_equal(i4, want) and np.array_equal(p4, pw)
