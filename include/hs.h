@@ -269,6 +269,22 @@ hs_status hs_lse_forward(const hs_plan* plan, const void* fop, int64_t ld, float
 hs_status hs_lse_backward(const hs_plan* plan, const void* fop, int64_t ld, const double* lse,
                           float tau, const double* gscale, float* dfop, void* work, void* stream);
 
+/* hs_lse_forward for callers that cannot allocate (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation): the same
+ * kernels and results (bitwise) as hs_lse_forward, with no workspace
+ * argument.  Its scratch (the per-block pairs, at most 512 KB: 4096 blocks
+ * x 16 planes x 2 floats) is a static device array, one per GPU, held until
+ * the process ends; its address is looked up on the first call on each
+ * device.  It calls no hipMalloc or hipFree and copies no plan tables (the
+ * tile kernel takes the schedule if hs_plan_upload or an earlier call put it
+ * on the device, else contiguous chunks, with the same results).  Every call
+ * on a GPU shares that GPU's scratch: calls that overlap on one GPU (two
+ * streams, two threads) race.  fp32 single-FOP plans with the paper's
+ * mapping only (HS_ERR_UNSUPPORTED otherwise); HS_ERR_INVALID if the grid's
+ * pairs would not fit the scratch (not reachable with the planner's grid). */
+hs_status hs_lse_forward_noalloc(const hs_plan* plan, const void* fop, int64_t ld, float tau, double* lse,
+                                 double* loss, void* stream);
+
 /* Host check of counts copied back from hs_detect: HS_ERR_OVERFLOW when
  * counts[n_hp] > capacity, HS_OK otherwise. */
 hs_status hs_check_counts(const int64_t* counts_host, int32_t n_hp, int64_t capacity);

@@ -83,6 +83,7 @@ _SIG = {
     "hs_sum_backward": ([_P, _P, _P, _P, _P], ctypes.c_int),
     "hs_lse_workspace_bytes": ([_P], ctypes.c_size_t),
     "hs_lse_forward": ([_P, _P, _I64, ctypes.c_float, _P, _P, _P, _P], ctypes.c_int),
+    "hs_lse_forward_noalloc": ([_P, _P, _I64, ctypes.c_float, _P, _P, _P], ctypes.c_int),
     "hs_lse_backward": ([_P, _P, _I64, _P, ctypes.c_float, _P, _P, _P, _P],
                         ctypes.c_int),
     "hs_check_counts": ([ctypes.POINTER(ctypes.c_int64), ctypes.c_int32, _I64], ctypes.c_int),
@@ -249,6 +250,12 @@ def hs_lse_forward(handle, fop, ld, tau, lse, loss, work, stream=None):
     _need_cuda(fop, lse, loss, work)
     _check(_c_hs_lse_forward(handle, _ptr(fop), int(ld), float(tau), _ptr(lse), _ptr(loss), _ptr(work),
                              _stream(stream)), "hs_lse_forward")
+
+
+def hs_lse_forward_noalloc(handle, fop, ld, tau, lse, loss, stream=None):
+    _need_cuda(fop, lse, loss)
+    _check(_c_hs_lse_forward_noalloc(handle, _ptr(fop), int(ld), float(tau), _ptr(lse), _ptr(loss),
+                                     _stream(stream)), "hs_lse_forward_noalloc")
 
 
 def hs_lse_backward(handle, fop, ld, lse, tau, gscale, dfop, work, stream=None):

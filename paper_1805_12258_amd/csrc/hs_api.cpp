@@ -306,6 +306,25 @@ hs_status device_tables(const hs_plan* p, hipStream_t stream, DevTabs* t)
     return HS_OK;
 }
 
+// The tables already on the current device, copying nothing (what is not
+// there yet is null: the tile kernels then take contiguous chunks, with the
+// same results).  HS_ERR_INVALID for a stream of another device.
+hs_status device_tables_present(const hs_plan* p, hipStream_t stream, DevTabs* t)
+{
+    *t = DevTabs{};
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return HS_ERR_HIP;
+    if (stream) {
+        hipDevice_t sd = 0;
+        if (hipStreamGetDevice(stream, &sd) != hipSuccess || (int)sd != dev) return HS_ERR_INVALID;
+    }
+    std::lock_guard<std::mutex> g(p->mu);
+    t->walk = p->d_walk[dev];
+    t->sched = p->d_sched[dev];
+    t->batch = p->d_tables[dev];
+    return HS_OK;
+}
+
 hsk::WalkArgs walk_args(const hs_plan* p, const unsigned char* tab)
 {
     hsk::WalkArgs a{};
@@ -796,7 +815,43 @@ int lse_grid(const hs_plan* p)
     return (int)std::max<int64_t>(g, 1);
 }
 
+// The fused statistic (fp32 plans): the planes are formed tile by tile and
+// never stored; `part` holds lse_grid(p) x H (max, sum) pairs.
+hs_status lse_forward_fused(const hs_plan* p, const void* fop, int64_t ld, float tau, double* lse, double* loss,
+                            float* part, const DevTabs& t, hipStream_t s)
+{
+    const int g = lse_grid(p);
+    hsk::TileArgs a = tile_args(p, fop, ld, t);
+    a.lse_part = part;
+    a.lse_c = (float)(1.4426950408889634 / (double)p->scale / (double)tau);
+    hipError_t e = hsk::launch_fused(hsk::kModeLse, p->dtype, p->H, a, p->tiles_total, g, p->lds_bytes, s);
+    if (e != hipSuccess) return HS_ERR_HIP;
+    e = hsk::launch_lse_fused_final(a.lse_part, g, p->H, 1.0 / (double)p->scale, (double)tau, lse, s);
+    if (e != hipSuccess) return HS_ERR_HIP;
+    return loss ? from_hip(hsk::launch_lse_loss(lse, p->H, (double)tau, loss, s)) : HS_OK;
+}
+
 }  // namespace
+
+hs_status hs_lse_forward_noalloc(const hs_plan* p, const void* fop, int64_t ld, float tau, double* lse,
+                                 double* loss, void* stream)
+{
+    if (!p || p->n_fops != 0 || !lse || !tau_ok(tau)) return HS_ERR_INVALID;
+    if (p->mapping != HS_MAP_PAPER || p->dtype != HS_DTYPE_F32) return HS_ERR_UNSUPPORTED;
+    if (!fop_ok(p, fop, ld, p->N)) return HS_ERR_INVALID;
+    try {
+        hipStream_t s = (hipStream_t)stream;
+        if ((size_t)lse_grid(p) * p->H * 2 * sizeof(float) > hsk::kNoAllocScratchBytes) return HS_ERR_INVALID;
+        void* scratch = nullptr;
+        if (hsk::noalloc_scratch(&scratch) != hipSuccess) return HS_ERR_HIP;
+        DevTabs t;
+        const hs_status st = device_tables_present(p, s, &t);
+        if (st != HS_OK) return st;
+        return lse_forward_fused(p, fop, ld, tau, lse, loss, static_cast<float*>(scratch), t, s);
+    } catch (...) {
+        return HS_ERR_HIP;
+    }
+}
 
 hs_status hs_lse_forward(const hs_plan* p, const void* fop, int64_t ld, float tau, double* lse,
                          double* loss, void* work, void* stream)
@@ -809,19 +864,7 @@ hs_status hs_lse_forward(const hs_plan* p, const void* fop, int64_t ld, float ta
         DevTabs t;
         const hs_status st = device_tables(p, s, &t);
         if (st != HS_OK) return st;
-        if (p->dtype == HS_DTYPE_F32) {
-            // fused: the planes are formed tile by tile and never stored
-            const int g = lse_grid(p);
-            hsk::TileArgs a = tile_args(p, fop, ld, t);
-            a.lse_part = static_cast<float*>(work);
-            a.lse_c = (float)(1.4426950408889634 / (double)p->scale / (double)tau);
-            hipError_t e = hsk::launch_fused(hsk::kModeLse, p->dtype, p->H, a, p->tiles_total, g,
-                                             p->lds_bytes, s);
-            if (e != hipSuccess) return HS_ERR_HIP;
-            e = hsk::launch_lse_fused_final(a.lse_part, g, p->H, 1.0 / (double)p->scale, (double)tau, lse, s);
-            if (e != hipSuccess) return HS_ERR_HIP;
-            return loss ? from_hip(hsk::launch_lse_loss(lse, p->H, (double)tau, loss, s)) : HS_OK;
-        }
+        if (p->dtype == HS_DTYPE_F32) return lse_forward_fused(p, fop, ld, tau, lse, loss, static_cast<float*>(work), t, s);
         float* planes = static_cast<float*>(work);
         void* tail = static_cast<char*>(work) + round256(plane_bytes(p) * p->H);
         hsk::TileArgs a = tile_args(p, fop, ld, t);

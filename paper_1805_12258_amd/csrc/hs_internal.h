@@ -259,6 +259,12 @@ enum Mode { kModeDetect = 0, kModeSum = 1, kModeLse = 2, kModeWeights = 3 };
 // the workspace are sized for it).
 constexpr int kLseMaxBlocks = 4096;
 
+// Static device scratch of the allocation-free entry points: the fused
+// statistic's per-block pairs at its largest grid and plane count.
+constexpr size_t kNoAllocScratchBytes = (size_t)kLseMaxBlocks * kMaxH * 2 * sizeof(float);
+// Address of this GPU's copy (looked up once per device).
+hipError_t noalloc_scratch(void** ptr);
+
 // LDS bytes of the fused kernel: fp32 storage double-buffers the fp32
 // staging; 16-bit storage double-buffers the raw staging and converts into
 // one fp32 staging buffer.
