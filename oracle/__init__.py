@@ -262,3 +262,33 @@ def select_top(idx, pw, N, H, n_cand):
         out_i[kk - 1, :len(order)] = idx[order]
         out_p[kk - 1, :len(order)] = pw[order]
     return out_i, out_p, cnt
+
+
+def select_last(idx, pw, N, H, n_cand, order="alg2", T=None):
+    """Per-plane capped lists under the "last N_cand" policy (Sec. IV-A: when
+    a plane has more than N_cand candidates, the ones met last in processing
+    order are kept).  order "alg2": the loop order of Algorithm 2 (bin j
+    outer, then template i, plane k inner), so within a plane the candidates
+    arrive by ascending (j, row); "alg1": Algorithm 1 (plane, template, bin),
+    ascending (row, j), i.e. ascending word within a plane.  Returns
+    (idx [H][n_cand], pw [H][n_cand], counts [H]); each plane's kept entries
+    in processing order (the earliest kept first), unused slots 0."""
+    idx = np.asarray(idx, dtype=np.uint32)
+    pw = np.asarray(pw, dtype=np.float32)
+    r, k, j = unpack(idx, N, H)
+    out_i = np.zeros((H, n_cand), dtype=np.uint32)
+    out_p = np.zeros((H, n_cand), dtype=np.float32)
+    cnt = np.zeros(H, dtype=np.int64)
+    for kk in range(1, H + 1):
+        sel = np.nonzero(k == kk)[0]
+        if order == "alg2":
+            seq = sel[np.lexsort((r[sel], j[sel]))]          # ascending (j, row)
+        elif order == "alg1":
+            seq = sel[np.lexsort((j[sel], r[sel]))]          # ascending (row, j)
+        else:
+            raise ValueError("order must be alg1 or alg2")
+        keep = seq[max(0, len(seq) - n_cand):]
+        cnt[kk - 1] = len(keep)
+        out_i[kk - 1, :len(keep)] = idx[keep]
+        out_p[kk - 1, :len(keep)] = pw[keep]
+    return out_i, out_p, cnt

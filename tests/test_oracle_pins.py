@@ -437,6 +437,39 @@ def test_select_top_against_sorted_brute_force():
             assert got_bits == [int(np.float32(p).view(np.uint32)) for _, p in want]
 
 
+def test_select_last_against_streaming_process():
+    """The "last N_cand" lists against the process they describe: run the
+    loops of Algorithm 2 (j, then i, then k) or Algorithm 1 (k, i, j) over
+    thresholded planes of a tiny FOP, appending each hit to its plane's
+    ring of N_cand slots (Sec. IV-A: the last N_cand are kept), and read the
+    rings out oldest first."""
+    from collections import deque
+    T, N, H = 9, 300, 6
+    fop = rand_exp(T, N, 23)
+    ta = np.stack([np.full(T, k + 1.5 * math.sqrt(k), np.float32) for k in range(1, H + 1)])
+    hp = brute.planes_alg2_f32(fop, H)
+    idx, pw, cnt = oracle.detect_f32(fop, H, ta)
+    assert cnt[H] > 200
+    for order in ("alg2", "alg1"):
+        for n_cand in (1, 7, 40, 10 ** 6):
+            rings = [deque(maxlen=n_cand) for _ in range(H)]
+            if order == "alg2":
+                loops = ((k, r, j) for j in range(N) for r in range(T) for k in range(1, H + 1))
+            else:
+                loops = ((k, r, j) for k in range(1, H + 1) for r in range(T) for j in range(N))
+            for k, r, j in loops:
+                v = hp[k - 1, r, j]
+                if v > ta[k - 1, r]:
+                    rings[k - 1].append((oracle.pack(r, k, j, N, H), v))
+            perm = np.random.default_rng(n_cand).permutation(len(idx))   # input order must not matter
+            oi, op, oc = oracle.select_last(idx[perm], pw[perm], N, H, n_cand, order=order)
+            for k in range(1, H + 1):
+                want = list(rings[k - 1])
+                assert oc[k - 1] == len(want)
+                assert [int(w) for w in oi[k - 1, :len(want)]] == [w for w, _ in want], (order, n_cand, k)
+                assert np.array_equal(op[k - 1, :len(want)], np.array([v for _, v in want], np.float32))
+
+
 # --- fractional variant: HPF_k(i,j) = sum_{m=1..k} FOP(floor(m i/k), floor(m j/k)) ---
 # (the incoherent-sum reading of "the FOP at the fractions m/k of each point";
 # not Eq. 1-2 of the paper, which it matches only for k <= 2)
