@@ -180,15 +180,33 @@ hs_status hs_detect(const hs_plan* plan, const void* fop, int64_t ld, const floa
 /* Per-plane capped candidate lists: the N_hp x N_cand list of Sec. III.
  * Input: a complete candidate list of this plan (cand[0..n), e.g. the first
  * counts[n_hp] entries of hs_detect when they fit its capacity), not
- * modified.  Output: out [n_hp][n_cand]; row k-1 holds the n_cand largest
- * powers of plane k, ties to the smaller CL1 word, in that order (powers
- * ordered by the IEEE total order of their bits, -0 below +0), and
- * out_counts [n_hp] int64 (device) the number written to each row,
- * min(n_cand, candidates of plane k); entries past that are not written.
+ * modified.  Output: out [n_hp][n_cand]; row k-1 holds min(n_cand,
+ * candidates of plane k) entries chosen by `policy`, and out_counts [n_hp]
+ * int64 (device) that number; entries past it are not written.
+ *   HS_SELECT_TOP       the largest powers, ties to the smaller CL1 word,
+ *                       listed in that order (powers in the IEEE total
+ *                       order of their bits, -0 below +0);
+ *   HS_SELECT_LAST_ALG2 the candidates met last when the loops run in
+ *                       Algorithm 2 order (bin, template, plane), i.e. the
+ *                       largest (bin, row) of the plane, listed oldest first
+ *                       (Sec. IV-A: the last N_cand are kept);
+ *   HS_SELECT_LAST_ALG1 the same for Algorithm 1 order (plane, template,
+ *                       bin): the largest (row, bin), oldest first.
  * Deterministic: the same set gives the same lists in any input order.
- * `work`: device memory of hs_select_workspace_bytes(plan, n) bytes (four
- * copies of the list plus rocPRIM scratch).  Stream-ordered. */
+ * n_cand <= 1024: a bounded selection (partition by plane, then per plane a
+ * radix select on the policy's key and an LDS sort of the kept entries);
+ * larger caps: HS_SELECT_TOP by two full radix sorts, the other policies
+ * HS_ERR_UNSUPPORTED.  `work`: device memory of
+ * hs_select_workspace_bytes(plan, n) bytes.  Stream-ordered.  hs_select_top
+ * is hs_select with HS_SELECT_TOP. */
+typedef enum hs_select_policy {
+    HS_SELECT_TOP = 0,
+    HS_SELECT_LAST_ALG2 = 1,
+    HS_SELECT_LAST_ALG1 = 2
+} hs_select_policy;
 size_t hs_select_workspace_bytes(const hs_plan* plan, int64_t n);
+hs_status hs_select(const hs_plan* plan, const hs_cand* cand, int64_t n, int32_t n_cand, int32_t policy,
+                    hs_cand* out, int64_t* out_counts, void* work, void* stream);
 hs_status hs_select_top(const hs_plan* plan, const hs_cand* cand, int64_t n, int32_t n_cand, hs_cand* out,
                         int64_t* out_counts, void* work, void* stream);
 
@@ -203,6 +221,14 @@ hs_status hs_select_top(const hs_plan* plan, const hs_cand* cand, int64_t n, int
 size_t hs_singlehp_workspace_bytes(const hs_plan* plan);
 hs_status hs_detect_singlehp(const hs_plan* plan, const float* fop, int64_t ld, const float* ta,
                              hs_cand* out, int64_t capacity, int64_t* counts, void* work, void* stream);
+
+/* The single-launch SingleHP kernel (Sec. V-A evaluates both): the same
+ * planes through the same two plane buffers, all N_hp of them formed in
+ * order inside one launch (a point of HP_k needs only the same point of
+ * HP_{k-1}, so each thread carries its own points from plane to plane).
+ * Arguments, workspace and results as hs_detect_singlehp. */
+hs_status hs_detect_singlehp_one(const hs_plan* plan, const float* fop, int64_t ld, const float* ta,
+                                 hs_cand* out, int64_t capacity, int64_t* counts, void* work, void* stream);
 
 /* hs_detect over a batch of FOPs of different lengths in one launch of a
  * persistent kernel.  Once the plan's tables are on the device

@@ -75,8 +75,10 @@ _SIG = {
     "hs_detect_batched": ([_P, _P, _P, _P, _P, _P, _P, _P, _P], ctypes.c_int),
     "hs_select_workspace_bytes": ([_P, _I64], ctypes.c_size_t),
     "hs_select_top": ([_P, _P, _I64, ctypes.c_int32, _P, _P, _P, _P], ctypes.c_int),
+    "hs_select": ([_P, _P, _I64, ctypes.c_int32, ctypes.c_int32, _P, _P, _P, _P], ctypes.c_int),
     "hs_singlehp_workspace_bytes": ([_P], ctypes.c_size_t),
     "hs_detect_singlehp": ([_P, _P, _I64, _P, _P, _I64, _P, _P, _P], ctypes.c_int),
+    "hs_detect_singlehp_one": ([_P, _P, _I64, _P, _P, _I64, _P, _P, _P], ctypes.c_int),
     "hs_sort_workspace_bytes": ([_I64], ctypes.c_size_t),
     "hs_sort_candidates": ([_P, _I64, _P, _P], ctypes.c_int),
     "hs_backward_workspace_bytes": ([_P], ctypes.c_size_t),
@@ -177,6 +179,16 @@ def hs_select_workspace_bytes(handle, n):
     return int(_c_hs_select_workspace_bytes(handle, int(n)))
 
 
+HS_SELECT_TOP, HS_SELECT_LAST_ALG2, HS_SELECT_LAST_ALG1 = 0, 1, 2
+_POLICIES = {"top": HS_SELECT_TOP, "last_alg2": HS_SELECT_LAST_ALG2, "last_alg1": HS_SELECT_LAST_ALG1}
+
+
+def hs_select(handle, cand, n, n_cand, policy, out, out_counts, work, stream=None):
+    _need_cuda(cand, out, out_counts, work)
+    _check(_c_hs_select(handle, _ptr(cand), int(n), int(n_cand), int(policy), _ptr(out), _ptr(out_counts),
+                        _ptr(work), _stream(stream)), "hs_select")
+
+
 def hs_select_top(handle, cand, n, n_cand, out, out_counts, work, stream=None):
     _need_cuda(cand, out, out_counts, work)
     _check(_c_hs_select_top(handle, _ptr(cand), int(n), int(n_cand), _ptr(out), _ptr(out_counts),
@@ -191,6 +203,12 @@ def hs_detect_singlehp(handle, fop, ld, ta, out, capacity, counts, work, stream=
     _need_cuda(fop, ta, counts, work)
     _check(_c_hs_detect_singlehp(handle, _ptr(fop), int(ld), _ptr(ta), _ptr(out), int(capacity),
                                  _ptr(counts), _ptr(work), _stream(stream)), "hs_detect_singlehp")
+
+
+def hs_detect_singlehp_one(handle, fop, ld, ta, out, capacity, counts, work, stream=None):
+    _need_cuda(fop, ta, counts, work)
+    _check(_c_hs_detect_singlehp_one(handle, _ptr(fop), int(ld), _ptr(ta), _ptr(out), int(capacity),
+                                     _ptr(counts), _ptr(work), _stream(stream)), "hs_detect_singlehp_one")
 
 
 def hs_plan_schedule(handle):
@@ -403,21 +421,28 @@ class Plan:
         hs_detect(self.handle, fop, ld, ta, out, capacity, counts, stream)
         return out, counts
 
-    def select_top(self, cand, n, n_cand, stream=None):
+    def select(self, cand, n, n_cand, policy="top", stream=None):
         """Per-plane capped lists from the first n rows of a detect output
-        ([cap][2] int32): returns ([H][n_cand][2] int32, [H] int64)."""
+        ([cap][2] int32) under a policy ("top", "last_alg2", "last_alg1"):
+        returns ([H][n_cand][2] int32, [H] int64)."""
         dev = cand.device
         self._cand_out(cand, int(n), dev)
+        pol = _POLICIES[policy] if isinstance(policy, str) else int(policy)
         with self._alloc(stream):
             out = torch.zeros((self.n_hp, int(n_cand), 2), dtype=torch.int32, device=dev)
             cnt = torch.empty(self.n_hp, dtype=torch.int64, device=dev)
             work = self._work(hs_select_workspace_bytes(self.handle, n), dev)
-        hs_select_top(self.handle, cand, n, n_cand, out, cnt, work, stream)
+        hs_select(self.handle, cand, n, n_cand, pol, out, cnt, work, stream)
         return out, cnt
 
-    def detect_singlehp(self, fop, ta, capacity=None, out=None, counts=None, stream=None):
-        """The SingleHP baseline (plane by plane through memory); same
-        outputs as detect()."""
+    def select_top(self, cand, n, n_cand, stream=None):
+        """select() with the "top" policy."""
+        return self.select(cand, n, n_cand, "top", stream)
+
+    def detect_singlehp(self, fop, ta, capacity=None, out=None, counts=None, stream=None, single_launch=False):
+        """The SingleHP baseline (plane by plane through memory, one launch
+        per plane or, with single_launch, one launch); same outputs as
+        detect()."""
         ld = self._fop(fop)
         dev = fop.device
         self._ta(ta, dev)
@@ -432,7 +457,8 @@ class Plan:
             work = self._work(hs_singlehp_workspace_bytes(self.handle), dev)
         self._cand_out(out, capacity, dev)
         self._counts(counts, dev)
-        hs_detect_singlehp(self.handle, fop, ld, ta, out, capacity, counts, work, stream)
+        (hs_detect_singlehp_one if single_launch else hs_detect_singlehp)(
+            self.handle, fop, ld, ta, out, capacity, counts, work, stream)
         return out, counts
 
     def backward(self, g, dfop=None, stream=None):

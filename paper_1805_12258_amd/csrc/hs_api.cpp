@@ -14,7 +14,7 @@ namespace hsk {
 // SingleHP baseline (hs_singlehp.hip)
 hipError_t launch_singlehp(const float* fop, int64_t ld, int T, int N, int H, const float* ta, hs_cand* out,
                            int64_t cap, unsigned long long* counts, int s_row, int s_bin, float* work,
-                           hipStream_t s);
+                           bool single_launch, hipStream_t s);
 // Per-plane capped lists (hs_select.hip)
 hipError_t select_workspace(int64_t n, int end_bit, size_t* bytes);
 hipError_t select_top(const uint64_t* cand, int64_t n, int H, int s_bin, int s_k, int n_cand, uint64_t* out,
@@ -637,20 +637,33 @@ size_t hs_select_workspace_bytes(const hs_plan* p, int64_t n)
     if (!p || n < 0) return 0;
     size_t bytes = 0;
     if (hsk::select_workspace(n, 32 + p->s_k, &bytes) != hipSuccess) return 0;
-    return bytes;
+    return std::max(bytes, hsk::select_bounded_workspace(n, p->H, hsk::kSelLdsCand));
+}
+
+hs_status hs_select(const hs_plan* p, const hs_cand* cand, int64_t n, int32_t n_cand, int32_t policy, hs_cand* out,
+                    int64_t* out_counts, void* work, void* stream)
+{
+    if (!p || n < 0 || n_cand < 1 || !out || !out_counts || !work) return HS_ERR_INVALID;
+    if (policy != HS_SELECT_TOP && policy != HS_SELECT_LAST_ALG2 && policy != HS_SELECT_LAST_ALG1)
+        return HS_ERR_INVALID;
+    if (n > 0 && !cand) return HS_ERR_INVALID;
+    try {
+        const uint64_t* c = reinterpret_cast<const uint64_t*>(cand);
+        uint64_t* o = reinterpret_cast<uint64_t*>(out);
+        hipStream_t s = (hipStream_t)stream;
+        if (n_cand <= hsk::kSelLdsCand && n <= (int64_t)UINT32_MAX)
+            return from_hip(hsk::select_bounded(c, n, p->H, p->s_bin, p->s_k, policy, n_cand, o, out_counts, work, s));
+        if (policy != HS_SELECT_TOP) return HS_ERR_UNSUPPORTED;
+        return from_hip(hsk::select_top(c, n, p->H, p->s_bin, p->s_k, n_cand, o, out_counts, work, s));
+    } catch (...) {
+        return HS_ERR_HIP;
+    }
 }
 
 hs_status hs_select_top(const hs_plan* p, const hs_cand* cand, int64_t n, int32_t n_cand, hs_cand* out,
                         int64_t* out_counts, void* work, void* stream)
 {
-    if (!p || n < 0 || n_cand < 1 || !out || !out_counts || !work) return HS_ERR_INVALID;
-    if (n > 0 && !cand) return HS_ERR_INVALID;
-    try {
-        return from_hip(hsk::select_top(reinterpret_cast<const uint64_t*>(cand), n, p->H, p->s_bin, p->s_k, n_cand,
-                                        reinterpret_cast<uint64_t*>(out), out_counts, work, (hipStream_t)stream));
-    } catch (...) {
-        return HS_ERR_HIP;
-    }
+    return hs_select(p, cand, n, n_cand, HS_SELECT_TOP, out, out_counts, work, stream);
 }
 
 size_t hs_singlehp_workspace_bytes(const hs_plan* p)
@@ -659,8 +672,10 @@ size_t hs_singlehp_workspace_bytes(const hs_plan* p)
     return 2 * (size_t)((p->T * p->N + 63) & ~(int64_t)63) * sizeof(float);
 }
 
-hs_status hs_detect_singlehp(const hs_plan* p, const float* fop, int64_t ld, const float* ta, hs_cand* out,
-                             int64_t capacity, int64_t* counts, void* work, void* stream)
+namespace {
+
+hs_status singlehp(const hs_plan* p, const float* fop, int64_t ld, const float* ta, hs_cand* out, int64_t capacity,
+                   int64_t* counts, void* work, bool single_launch, void* stream)
 {
     if (!p || p->n_fops != 0 || !ta || !counts || !work || capacity < 0) return HS_ERR_INVALID;
     if (p->dtype != HS_DTYPE_F32 || p->mapping != HS_MAP_PAPER) return HS_ERR_UNSUPPORTED;
@@ -672,10 +687,24 @@ hs_status hs_detect_singlehp(const hs_plan* p, const float* fop, int64_t ld, con
         if (e != hipSuccess) return HS_ERR_HIP;
         return from_hip(hsk::launch_singlehp(fop, ld, (int)p->T, (int)p->N, p->H, ta, out, capacity,
                                              reinterpret_cast<unsigned long long*>(counts), p->s_row, p->s_bin,
-                                             static_cast<float*>(work), s));
+                                             static_cast<float*>(work), single_launch, s));
     } catch (...) {
         return HS_ERR_HIP;
     }
+}
+
+}  // namespace
+
+hs_status hs_detect_singlehp(const hs_plan* p, const float* fop, int64_t ld, const float* ta, hs_cand* out,
+                             int64_t capacity, int64_t* counts, void* work, void* stream)
+{
+    return singlehp(p, fop, ld, ta, out, capacity, counts, work, false, stream);
+}
+
+hs_status hs_detect_singlehp_one(const hs_plan* p, const float* fop, int64_t ld, const float* ta, hs_cand* out,
+                                 int64_t capacity, int64_t* counts, void* work, void* stream)
+{
+    return singlehp(p, fop, ld, ta, out, capacity, counts, work, true, stream);
 }
 
 hs_status hs_detect_batched(const hs_plan* p, const void* const* fops, const int64_t* lds,

@@ -280,6 +280,12 @@ hipError_t launch_batched(int dtype, int H, const BatchArgs& a, int grid, int ld
                           hipStream_t s);
 hipError_t launch_zero_i64(int64_t* p, int64_t n, hipStream_t s);
 
+// Bounded per-plane selection (policies of hs_select, n_cand <= kSelLdsCand).
+constexpr int kSelLdsCand = 1024;
+hipError_t select_bounded(const uint64_t* cand, int64_t n, int H, int s_bin, int s_k, int policy, int n_cand,
+                          uint64_t* out, int64_t* out_counts, void* work, hipStream_t s);
+size_t select_bounded_workspace(int64_t n, int H, int n_cand);
+
 // Fractional mapping (HP_k = sum_{m<=k} FOP(floor(m i/k), floor(m j/k))):
 // planes (hp) or detection (ta, out, cap, counts), single FOP, N <= 2^24.
 constexpr int64_t kFracMaxBins = (int64_t)1 << 24;

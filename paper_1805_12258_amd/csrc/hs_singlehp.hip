@@ -4,7 +4,12 @@
 // formed.  It is the method the paper's MultipleHP improves on; here it
 // serves as the measured reference point for the fused kernels on the same
 // GPU.  The sums are the fused kernels' (same order, fp32), so planes and
-// candidate sets are bitwise the same.
+// candidate sets are bitwise the same.  Two forms, as evaluated in Sec. V-A:
+// multiple launches (one per plane) and a single launch that walks the
+// planes in order inside the kernel.  HP_k at a point needs only HP_{k-1}
+// at the same point, and every thread keeps the same points for every
+// plane, so the single launch needs no grid-wide barrier between planes: a
+// thread reads back the plane values it wrote itself.
 #include <hip/hip_runtime.h>
 
 #include "hs_internal.h"
@@ -17,12 +22,11 @@ constexpr int kSThreads = 256;
 
 // Plane k: each thread forms 4 consecutive bins of one row.  The loop bound
 // is uniform per block so every wave votes on every step.
-__global__ __launch_bounds__(kSThreads) void k_single_plane(const float* __restrict__ fop, int64_t ld, int T,
-                                                           int N, int c, int k, const float* __restrict__ prev,
-                                                           float* __restrict__ cur, const float* __restrict__ ta,
-                                                           hs_cand* __restrict__ out, int64_t cap,
-                                                           unsigned long long* __restrict__ counts, int s_row,
-                                                           int s_bin, int H)
+__device__ __forceinline__ void single_plane_pass(const float* __restrict__ fop, int64_t ld, int T, int N, int c,
+                                                  int k, const float* prev, float* cur,
+                                                  const float* __restrict__ ta, hs_cand* __restrict__ out,
+                                                  int64_t cap, unsigned long long* __restrict__ counts, int s_row,
+                                                  int s_bin, int H)
 {
     const int64_t nq = (N + 3) / 4;
     const int64_t total = (int64_t)T * nq;
@@ -75,20 +79,57 @@ __global__ __launch_bounds__(kSThreads) void k_single_plane(const float* __restr
     }
 }
 
+__global__ __launch_bounds__(kSThreads) void k_single_plane(const float* __restrict__ fop, int64_t ld, int T,
+                                                           int N, int c, int k, const float* prev, float* cur,
+                                                           const float* __restrict__ ta,
+                                                           hs_cand* __restrict__ out, int64_t cap,
+                                                           unsigned long long* __restrict__ counts, int s_row,
+                                                           int s_bin, int H)
+{
+    single_plane_pass(fop, ld, T, N, c, k, prev, cur, ta, out, cap, counts, s_row, s_bin, H);
+}
+
+// The single launch: planes 1..H in order, ping-ponging between the two
+// plane buffers as the multiple launches do.
+__global__ __launch_bounds__(kSThreads) void k_single_all(const float* __restrict__ fop, int64_t ld, int T, int N,
+                                                         int c, float* buf0, float* buf1,
+                                                         const float* __restrict__ ta, hs_cand* __restrict__ out,
+                                                         int64_t cap, unsigned long long* __restrict__ counts,
+                                                         int s_row, int s_bin, int H)
+{
+    for (int k = 1; k <= H; ++k) {
+        float* prev = (k & 1) ? buf1 : buf0;
+        float* cur = (k & 1) ? buf0 : buf1;
+        single_plane_pass(fop, ld, T, N, c, k, prev, cur, ta, out, cap, counts, s_row, s_bin, H);
+    }
+}
+
+int single_grid(int T, int N)
+{
+    const int64_t quads = (int64_t)T * ((N + 3) / 4);
+    const int64_t want = (quads + kSThreads - 1) / kSThreads;
+    return (int)(want < 8192 ? (want < 1 ? 1 : want) : 8192);
+}
+
 }  // namespace
 
 // H launches, one per plane, through two plane buffers (`work`: 2 x T x N
-// fp32).  counts must be cleared by the caller.
+// fp32), or one launch (single_launch) through the same buffers.  counts
+// must be cleared by the caller.
 hipError_t launch_singlehp(const float* fop, int64_t ld, int T, int N, int H, const float* ta, hs_cand* out,
                            int64_t cap, unsigned long long* counts, int s_row, int s_bin, float* work,
-                           hipStream_t s)
+                           bool single_launch, hipStream_t s)
 {
     const int64_t plane = (int64_t)T * N;
-    const int64_t quads = (int64_t)T * ((N + 3) / 4);
-    const int64_t want = (quads + kSThreads - 1) / kSThreads;
-    const int grid = (int)(want < 8192 ? (want < 1 ? 1 : want) : 8192);
+    const int grid = single_grid(T, N);
     float* buf[2] = {work, work + ((plane + 63) & ~(int64_t)63)};
+    if (single_launch) {
+        hipLaunchKernelGGL(k_single_all, dim3(grid), dim3(kSThreads), 0, s, fop, ld, T, N, T / 2, buf[0], buf[1], ta,
+                           out, cap, counts, s_row, s_bin, H);
+        return hipGetLastError();
+    }
     for (int k = 1; k <= H; ++k) {
+        // plane k reads buf[k & 1] and writes buf[(k + 1) & 1], as in the single launch
         hipLaunchKernelGGL(k_single_plane, dim3(grid), dim3(kSThreads), 0, s, fop, ld, T, N, T / 2, k,
                            buf[k & 1], buf[(k + 1) & 1], ta, out, cap, counts, s_row, s_bin, H);
         const hipError_t e = hipGetLastError();

@@ -207,10 +207,12 @@ def test_reduced_precision_error_bound(name, dtype, u_in, sub):
     print("%s: max rel error (S >= 1) %.3g, max abs error %.3g" % (name, rel.max(), err.max()))
 
 
-@pytest.mark.parametrize("T,N,H", [(21, 1000, 8), (64, 4097, 16), (85, 256 * 7 + 3, 8), (1, 300, 3)])
+@pytest.mark.parametrize("T,N,H", [(21, 1000, 8), (64, 4097, 16), (85, 256 * 7 + 3, 8), (1, 300, 3),
+                                   (85, 300000, 8)])
 def test_singlehp_baseline(T, N, H):
-    """The SingleHP baseline (planes through memory) gives the oracle's
-    candidates and counts, bitwise, like the fused kernel."""
+    """The SingleHP baseline (planes through memory), with one launch per
+    plane and with a single launch, gives the oracle's candidates and
+    counts, bitwise, like the fused kernel."""
     print("case", T, N, H, flush=True)
     x = exp_plane(T, N, 500 + T + N)
     ta = random_thresholds(H, T, N + 3)
@@ -218,12 +220,14 @@ def test_singlehp_baseline(T, N, H):
     plan = hs.Plan(T, N, H)
     cap = H * T * N
     t = torch.from_numpy(np.ascontiguousarray(ta, dtype=np.float32)).cuda()
-    out, counts = plan.detect_singlehp(dev, t, capacity=cap)
-    counts = counts.cpu().numpy()
-    n = int(counts[-1])
-    a = out[:n].cpu().numpy()
-    got = (a[:, 0].view(np.uint32).copy(), a[:, 1].view(np.float32).copy(), counts)
-    assert_same_candidates(got, oracle_detect_sorted(store, H, ta))
+    want = oracle_detect_sorted(store, H, ta)
+    for single in (False, True):
+        out, counts = plan.detect_singlehp(dev, t, capacity=cap, single_launch=single)
+        counts = counts.cpu().numpy()
+        n = int(counts[-1])
+        a = out[:n].cpu().numpy()
+        got = (a[:, 0].view(np.uint32).copy(), a[:, 1].view(np.float32).copy(), counts)
+        assert_same_candidates(got, want)
 
 
 @pytest.mark.parametrize("T,N,H,n_cands", [(21, 1 << 14, 8, (1, 7, 100, 100000)), (33, 3000, 5, (2, 64)),
@@ -345,3 +349,68 @@ def test_wrappers_reject_bad_device_buffers():
         plan.backward(torch.zeros((H, T, N), device="cuda"), dfop=torch.zeros((T, N), dtype=torch.float64, device="cuda"))
     with pytest.raises(ValueError):
         plan.lse_backward(x, torch.zeros(H, dtype=torch.float32, device="cuda"), 0.5)
+
+
+def _oracle_select(policy, wi, wp, N, H, n_cand):
+    if policy == "top":
+        return oracle.select_top(wi, wp, N, H, n_cand)
+    return oracle.select_last(wi, wp, N, H, n_cand, order="alg2" if policy == "last_alg2" else "alg1")
+
+
+def _check_select(plan, out, n, wi, wp, N, H, n_cand, policy):
+    got, cnt = plan.select(out, n, n_cand, policy)
+    oi, op, oc = _oracle_select(policy, wi, wp, N, H, n_cand)
+    assert np.array_equal(cnt.cpu().numpy(), oc), (policy, n_cand)
+    g = got.cpu().numpy()
+    for k in range(H):
+        c = int(oc[k])
+        assert np.array_equal(g[k, :c, 0].view(np.uint32), oi[k, :c]), (policy, n_cand, k)
+        assert np.array_equal(g[k, :c, 1].view(np.uint32), op[k, :c].view(np.uint32)), (policy, n_cand, k)
+
+
+@pytest.mark.parametrize("policy", ["top", "last_alg2", "last_alg1"])
+def test_select_policies_ties_and_caps(policy):
+    """All three policies on a list with many exactly tied powers (integer
+    FOP): bitwise equal to the oracle's lists for caps from 1 to the bounded
+    selection's limit (1024); above it the top policy takes the sorting path
+    and the others are refused."""
+    T, N, H = 21, 1 << 14, 8
+    rng = np.random.default_rng(5)
+    x = torch.from_numpy(rng.integers(0, 5, size=(T, N)).astype(np.float32))
+    ta = np.repeat(np.array([k + 1.5 for k in range(1, H + 1)], dtype=np.float32)[:, None], T, axis=1)
+    dev, store = padded_device(x)
+    plan = hs.Plan(T, N, H)
+    out, counts = plan.detect(dev, torch.from_numpy(ta).cuda(), capacity=H * T * N)
+    n = int(counts[-1].item())
+    wi, wp, wc = oracle_detect_sorted(store, H, ta)
+    assert n == len(wi) > 100000
+    for n_cand in (1, 7, 200, 1023, 1024):
+        _check_select(plan, out, n, wi, wp, N, H, n_cand, policy)
+    if policy == "top":
+        _check_select(plan, out, n, wi, wp, N, H, 1025, policy)
+    else:
+        with pytest.raises(hs.HsError) as e:
+            plan.select(out, n, 1025, policy)
+        assert e.value.status == hs.HS_ERR_UNSUPPORTED
+    got, cnt = plan.select(out, 0, 4, policy)
+    assert np.array_equal(cnt.cpu().numpy(), np.zeros(H, dtype=np.int64))
+
+
+def test_select_refines_crowded_digits():
+    """Candidates crowded into a few bins of a long plane, so the leading
+    10-bit digit of the last-N_cand keys cannot separate them: the
+    selection refines with the next digits and still equals the oracle."""
+    T, N, H = 21, 1 << 20, 8
+    x = torch.zeros((T, N), dtype=torch.float32)
+    x[:, :1024] = 100.0
+    x[:, 5000] = 3.0
+    ta = np.full((H, T), 50.0, dtype=np.float32)
+    dev, store = padded_device(x)
+    plan = hs.Plan(T, N, H)
+    out, counts = plan.detect(dev, torch.from_numpy(ta).cuda(), capacity=1 << 20)
+    n = int(counts[-1].item())
+    wi, wp, wc = oracle_detect_sorted(store, H, ta)
+    assert n == len(wi) > 8 * 2048
+    for policy in ("last_alg2", "last_alg1", "top"):
+        for n_cand in (1, 300, 1024):
+            _check_select(plan, out, n, wi, wp, N, H, n_cand, policy)
