@@ -39,6 +39,11 @@ KERNEL_SOURCES = ["paper_1805_12258_amd/csrc/hs_fused_impl.h",
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "ska_detect_f32_traffic.json")
 
 
+def log(msg):
+    """Progress on stderr (the JSON line alone goes to stdout)."""
+    print("bench: " + msg, file=sys.stderr, flush=True)
+
+
 def kernel_source_hash():
     h = hashlib.sha256()
     for f in KERNEL_SOURCES:
@@ -87,35 +92,59 @@ def time_detect(plan, fop, ta, capacity, steps, warmup):
                 counts=counts.cpu().numpy().tolist())
 
 
-def cpu_baseline(fop_cpu, H, ta_np, max_bins, min_seconds=10.0):
+def host_threads():
+    """Threads for host work: the CPUs this process may run on, at most 16
+    (the host share of one GPU on the machines this runs on)."""
+    return max(1, min(16, len(os.sched_getaffinity(0))))
+
+
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(fop_cpu, H, ta_np, max_bins, seconds_per_run=4.0, runs=3):
     """The oracle (Algorithm 1 order, fp32, with detection) on the first
-    `max_bins` bins of the plane, repeated until `min_seconds` have passed (a
-    bounded sample of about 10 s of wall time): a prefix of bins is
-    self-contained, since every source bin floor(j/m) <= j."""
+    `max_bins` bins of the plane (a prefix of bins is self-contained: every
+    source bin floor(j/m) <= j): three timed runs of about 4 s each (a
+    bounded sample of the workload), the median reported, on host_threads()
+    threads; plus one single-thread pass on an eighth of the sample."""
     import oracle
     sample = np.ascontiguousarray(fop_cpu[:, :max_bins].numpy())
-    threads = len(os.sched_getaffinity(0))
-    threads = min(threads, 16)
+    threads = host_threads()
     cap = 1 << 22
     oracle.detect_f32(sample[:, :1024], H, ta_np, cap=cap, nthreads=threads)     # load + warm
-    reps = 0
-    t = time.perf_counter()
-    while True:
-        oracle.detect_f32(sample, H, ta_np, cap=cap, nthreads=threads)
-        reps += 1
-        dt = time.perf_counter() - t
-        if dt >= min_seconds:
-            break
-    pts = sample.shape[0] * sample.shape[1] * reps
+    rates = []
+    total_pts = 0
+    for _ in range(runs):
+        reps = 0
+        t = time.perf_counter()
+        while True:
+            oracle.detect_f32(sample, H, ta_np, cap=cap, nthreads=threads)
+            reps += 1
+            dt = time.perf_counter() - t
+            if dt >= seconds_per_run:
+                break
+        pts = sample.shape[0] * sample.shape[1] * reps
+        total_pts += pts
+        rates.append(pts / dt)
     t1 = time.perf_counter()
     one = np.ascontiguousarray(sample[:, :max_bins // 8])
     oracle.detect_f32(one, H, ta_np, cap=cap, nthreads=1)
     dt1 = time.perf_counter() - t1
-    return {"value": pts / dt, "unit": "points/s", "cores": threads, "kind": "oracle",
-            "sample": "first %d bins x %d templates of the same plane, %d passes (%.1f M points) "
-                      "in %.2f s on %d threads; 1 thread on %d bins: %.3g points/s"
-                      % (max_bins, sample.shape[0], reps, pts / 1e6, dt, threads, max_bins // 8,
-                         one.size / dt1)}
+    return {"value": float(np.median(rates)), "unit": "points/s", "cores": threads, "kind": "oracle",
+            "nproc": os.cpu_count(), "affinity": len(os.sched_getaffinity(0)), "cpu_model": cpu_model(),
+            "runs_points_per_s": rates,
+            "sample": "first %d bins x %d templates of the same plane (%.1f M points in all), median of %d "
+                      "runs of about %.0f s on %d threads (the CPU share of one GPU: at most 16 of the "
+                      "%d CPUs); 1 thread on %d bins: %.3g points/s"
+                      % (max_bins, sample.shape[0], total_pts / 1e6, runs, seconds_per_run, threads,
+                         os.cpu_count() or 0, max_bins // 8, one.size / dt1)}
 
 
 def candidate_words(out, counts):
@@ -143,7 +172,11 @@ def batched_leg(n_fops, steps, warmup, dev):
     cfg = synth.BATCHED
     T, H = cfg["n_temp"], cfg["n_hp"]
     lens = synth.batched_lengths(n_fops)
-    fops = [synth.make_batched_fop(f, n, device=dev) for f, n in enumerate(lens)]
+    fops = []
+    for f, n in enumerate(lens):
+        fops.append(synth.make_batched_fop(f, n, device=dev))
+        if (f + 1) % 128 == 0:
+            log("batched: %d FOPs drawn" % (f + 1))
     ta = torch.from_numpy(synth.thresholds(H, T)).to(dev)
     # room for twice the expected noise candidates of 16 planes
     caps = [int(2 * 180000 * n / (1 << 20)) + 4096 for n in lens]
@@ -182,10 +215,11 @@ def batched_leg(n_fops, steps, warmup, dev):
 
     plans = {n: hs.Plan(T, n, H) for n in sorted(set(lens))}
     single_counts = torch.empty_like(counts)
+    out_single = torch.empty_like(out)
 
     def per_fop():
         for f, x in enumerate(fops):
-            hs.hs_detect(plans[lens[f]].handle, x, x.stride(0), ta, out[offs[f]:], caps[f],
+            hs.hs_detect(plans[lens[f]].handle, x, x.stride(0), ta, out_single[offs[f]:], caps[f],
                          single_counts[f])
 
     for _ in range(max(1, warmup // 2)):
@@ -199,16 +233,118 @@ def batched_leg(n_fops, steps, warmup, dev):
     single_ms = e0.elapsed_time(e1) / steps
     if not torch.equal(single_counts, batched_counts):
         raise RuntimeError("batched and per-FOP candidate counts differ")
+    # the candidate lists themselves, FOP by FOP: (row, plane, bin, power
+    # bits), sorted; the batched word takes its bin field from the longest
+    # FOP, a per-FOP word from its own length
+    graph.replay()
+    torch.cuda.synchronize()
+
+    def canonical(o, n, info):
+        w = o[:n, 0].to(torch.int64) & 0xffffffff
+        kb = info["s_row"] - info["s_bin"]
+        r = w >> info["s_row"]
+        k = (w >> info["s_bin"]) & ((1 << kb) - 1)
+        j = w & ((1 << info["s_bin"]) - 1)
+        c = (r << 40) | (k << 32) | j
+        order = torch.argsort(c)
+        return c[order], o[:n, 1][order]
+
+    for f in range(n_fops):
+        n = int(batched_counts[f, -1].item())
+        if n > caps[f]:
+            continue                     # which entries are stored past the capacity is unspecified
+        ca, pa = canonical(out[offs[f]:], n, plan.info)
+        cb, pb = canonical(out_single[offs[f]:], n, plans[lens[f]].info)
+        if not (torch.equal(ca, cb) and torch.equal(pa, pb)):
+            raise RuntimeError("batched and per-FOP candidate lists differ (FOP %d)" % f)
     points = T * int(np.sum(lens))
     fop_bytes = 4 * points
-    del fops, out
+    del fops, out, out_single
     return {"n_fops": n_fops, "points": points, "fop_gb": fop_bytes / 1e9,
             "value": points / (batched_ms * 1e-3), "unit": "points/s",
             "ms_per_step": batched_ms, "hbm_gbs": fop_bytes / (batched_ms * 1e-3) / 1e9,
             "per_fop_launches_ms": single_ms, "vs_per_fop": single_ms / batched_ms,
             "candidates": int(batched_counts[:, -1].sum().item()),
+            "lists_equal_per_fop": True,
             "launch": "one persistent kernel replayed from a captured HIP graph",
             "autotuned": {"config": tuned, "on_fops": sub, "tuning_s": t_tune}}
+
+
+def precision_leg(n_fops, dev, threads):
+    """The precision workload: fp16 and bf16 storage of power x 1/8 for the
+    first n_fops FOPs of 85 x 2^21 fp32 (50 signals each, seeds 4*10^6 + f),
+    8 planes.  Per storage type, over every point of every plane of those
+    FOPs: the error of the 16-bit path's planes (hs_sum) against the fp64
+    oracle's planes of the fp32 FOP, as the largest relative error where the
+    fp64 sum is >= 1 and the largest absolute error, and the closed-form
+    bound |S - S64| <= (u_in + (k-1) 2^-24) S64 + k d_sub checked at every
+    point (all terms are >= 0; u_in = 2^-11 for fp16, 2^-8 for bf16; d_sub =
+    8 2^-25 for fp16 subnormals of x/8, 0 for bf16); and per plane the
+    precision and recall of the 16-bit candidate lists against the fp32
+    oracle's.  The FOPs are drawn on the GPU and copied to the host for the
+    oracle."""
+    import oracle
+    import paper_1805_12258_amd as hs
+    import synth
+    cfg = synth.PRECISION
+    T, N, H, scale = cfg["n_temp"], cfg["n_chan"], cfg["n_hp"], cfg["input_scale"]
+    ta_np = synth.thresholds(H, T)
+    ta = torch.from_numpy(ta_np).to(dev)
+    kinds = {"f16": (torch.float16, 2.0 ** -11, 8 * 2.0 ** -25), "bf16": (torch.bfloat16, 2.0 ** -8, 0.0)}
+    plans = {name: hs.Plan(T, N, H, dtype=name, input_scale=scale) for name in kinds}
+    res = {name: {"max_rel_err": 0.0, "max_abs_err": 0.0, "bound_held": True, "max_err_over_bound": 0.0,
+                  "tp": [0] * H, "fp": [0] * H, "fn": [0] * H} for name in kinds}
+    t0 = time.perf_counter()
+    for f in range(n_fops):
+        x = synth.make_precision_fop(f, device=dev)
+        xc = x.cpu().numpy()
+        ref = torch.from_numpy(oracle.sum_f64(xc, H, nthreads=threads)).to(dev)
+        iw, _, ic = oracle.detect_f32(xc, H, ta_np, nthreads=threads)
+        want = torch.from_numpy(iw.astype(np.int64)).to(dev)
+        for name, (dt, u_in, d_sub) in kinds.items():
+            r = res[name]
+            store = synth.quantize(x, dt, scale)
+            plan = plans[name]
+            hp = plan.sum(store)
+            for k in range(1, H + 1):
+                s64 = ref[k - 1]
+                err = (hp[k - 1].double() - s64).abs()
+                big = s64 >= 1.0
+                if bool(big.any()):
+                    r["max_rel_err"] = max(r["max_rel_err"], float((err[big] / s64[big]).max()))
+                r["max_abs_err"] = max(r["max_abs_err"], float(err.max()))
+                bound = (u_in + (k - 1) * 2.0 ** -24) * s64 + k * d_sub
+                r["bound_held"] = r["bound_held"] and bool((err <= bound * (1 + 1e-12)).all())
+                pos = bound > 0
+                r["max_err_over_bound"] = max(r["max_err_over_bound"], float((err[pos] / bound[pos]).max()))
+                del err, big, bound, pos
+            del hp
+            out, cnt = plan.detect(store, ta, capacity=1 << 22)
+            got = candidate_words(out, cnt)
+            kmask = (1 << plan.info["s_k"]) - 1
+            for k in range(1, H + 1):
+                g = got[((got >> plan.info["s_bin"]) & kmask) == k - 1]
+                w = want[((want >> plan.info["s_bin"]) & kmask) == k - 1]
+                common = int(torch.isin(g, w).sum().item())
+                r["tp"][k - 1] += common
+                r["fp"][k - 1] += len(g) - common
+                r["fn"][k - 1] += len(w) - common
+            del store, out
+        del x, ref, want
+        torch.cuda.empty_cache()
+        log("precision: FOP %d of %d done" % (f + 1, n_fops))
+    out = {"fops": n_fops, "of": cfg["n_fops"], "n_temp": T, "n_chan": N, "n_hp": H, "input_scale": scale,
+           "seconds": time.perf_counter() - t0}
+    for name, r in res.items():
+        prec = [r["tp"][k] / max(1, r["tp"][k] + r["fp"][k]) for k in range(H)]
+        rec = [r["tp"][k] / max(1, r["tp"][k] + r["fn"][k]) for k in range(H)]
+        out[name] = {"max_rel_err_s_ge_1": r["max_rel_err"], "max_abs_err": r["max_abs_err"],
+                     "p10_bound_held_every_point": r["bound_held"],
+                     "max_err_over_bound": r["max_err_over_bound"],
+                     "precision_per_k": prec, "recall_per_k": rec,
+                     "candidates_vs_fp32_oracle": {"common": sum(r["tp"]), "extra": sum(r["fp"]),
+                                                   "missed": sum(r["fn"])}}
+    return out
 
 
 def diff_leg(n_fops, steps, warmup, dev):
@@ -280,6 +416,8 @@ def main():
                     help="timed steps of the SingleHP baseline (0 skips it)")
     ap.add_argument("--diff-fops", type=int, default=16,
                     help="FOPs of the differentiation leg (0 skips it)")
+    ap.add_argument("--precision-fops", type=int, default=8,
+                    help="FOPs of the precision leg taken through the fp64 oracle (0 skips it)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one plain device copy of the FOP's size (counter scale)")
     args = ap.parse_args()
@@ -309,6 +447,7 @@ def main():
         del dst
 
     r = time_detect(plan, fop, ta, capacity, args.steps, args.warmup)
+    log("headline: %.4f ms per step" % r["ms_per_step"])
     ref_out, ref_counts = plan.detect(fop, ta, capacity=capacity)
     ref_words = candidate_words(ref_out, ref_counts)
     points = T * N
@@ -356,6 +495,7 @@ def main():
     torch.cuda.synchronize()
     sum_ms = e0.elapsed_time(e1) / 10
     sum_bytes = (4 + 4 * H) * points
+    log("hs_sum: %.3f ms" % sum_ms)
     line["sum"] = {"ms": sum_ms, "bytes_per_point": 4 + 4 * H,
                    "gbs": sum_bytes / (sum_ms * 1e-3) / 1e9,
                    "frac": sum_bytes / (sum_ms * 1e-3) / 1e9 / HBM_PEAK_GBS}
@@ -376,49 +516,58 @@ def main():
     line["sort"] = {"candidates": n_all, "ms": e0.elapsed_time(e1) / len(copies)}
     del srt, srt_work, copies
 
-    # per-plane capped lists (N_cand = 200) from the full candidate list
+    # per-plane capped lists (N_cand = 200, Sec. III) from the full candidate
+    # list, under each policy (bounded selection)
     n_all = int(ref_counts[-1].item())
     sel_out = torch.empty((H, 200, 2), dtype=torch.int32, device=dev)
     sel_cnt = torch.empty(H, dtype=torch.int64, device=dev)
     sel_work = torch.empty(max(hs.hs_select_workspace_bytes(plan.handle, n_all), 1), dtype=torch.uint8,
                            device=dev)
-    hs.hs_select_top(plan.handle, ref_out, n_all, 200, sel_out, sel_cnt, sel_work)
-    torch.cuda.synchronize()
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record()
-    for _ in range(10):
-        hs.hs_select_top(plan.handle, ref_out, n_all, 200, sel_out, sel_cnt, sel_work)
-    e1.record()
-    torch.cuda.synchronize()
-    line["capped"] = {"n_cand": 200, "candidates_in": n_all, "ms": e0.elapsed_time(e1) / 10,
-                      "kept": int(sel_cnt.sum().item())}
+    capped = {"n_cand": 200, "candidates_in": n_all}
+    for pname, pol in (("top", hs.HS_SELECT_TOP), ("last_alg2", hs.HS_SELECT_LAST_ALG2),
+                       ("last_alg1", hs.HS_SELECT_LAST_ALG1)):
+        hs.hs_select(plan.handle, ref_out, n_all, 200, pol, sel_out, sel_cnt, sel_work)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(20):
+            hs.hs_select(plan.handle, ref_out, n_all, 200, pol, sel_out, sel_cnt, sel_work)
+        e1.record()
+        torch.cuda.synchronize()
+        capped[pname + "_ms"] = e0.elapsed_time(e1) / 20
+    capped["kept"] = int(sel_cnt.sum().item())
+    line["capped"] = capped
+    log("capped lists: %s" % capped)
     del sel_work
 
     if args.singlehp_steps > 0:
-        # the paper's SingleHP method (planes through memory) on the same GPU
+        # the paper's SingleHP method (planes through memory) on the same GPU,
+        # with one launch per plane and with a single launch (Sec. V-A)
         out1 = torch.empty((capacity, 2), dtype=torch.int32, device=dev)
         cnt1 = torch.empty(H + 1, dtype=torch.int64, device=dev)
         work1 = torch.empty(hs.hs_singlehp_workspace_bytes(plan.handle), dtype=torch.uint8, device=dev)
         ld = fop.stride(0)
-        for _ in range(2):
-            hs.hs_detect_singlehp(plan.handle, fop, ld, ta, out1, capacity, cnt1, work1)
-        torch.cuda.synchronize()
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record()
-        for _ in range(args.singlehp_steps):
-            hs.hs_detect_singlehp(plan.handle, fop, ld, ta, out1, capacity, cnt1, work1)
-        e1.record()
-        torch.cuda.synchronize()
-        sh_ms = e0.elapsed_time(e1) / args.singlehp_steps
-        if not torch.equal(cnt1.cpu(), ref_counts.cpu()):
-            raise RuntimeError("SingleHP and fused candidate counts differ")
         # bytes per point: FOP read and HP_1 written, then per further plane
         # HP_{k-1} read, the stretched FOP value, HP_k written
         sb = 8 + 12 * (H - 1)
-        line["singlehp"] = {"ms_per_step": sh_ms, "value": points / (sh_ms * 1e-3), "unit": "points/s",
-                            "fused_speedup": sh_ms / r["ms_per_step"],
-                            "bytes_per_point": sb, "gbs": sb * points / (sh_ms * 1e-3) / 1e9,
-                            "method": "one launch per plane, each plane written and read back"}
+        line["singlehp"] = {"bytes_per_point": sb}
+        for lname, fn in (("multiple_launch", hs.hs_detect_singlehp), ("single_launch", hs.hs_detect_singlehp_one)):
+            for _ in range(2):
+                fn(plan.handle, fop, ld, ta, out1, capacity, cnt1, work1)
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for _ in range(args.singlehp_steps):
+                fn(plan.handle, fop, ld, ta, out1, capacity, cnt1, work1)
+            e1.record()
+            torch.cuda.synchronize()
+            sh_ms = e0.elapsed_time(e1) / args.singlehp_steps
+            if not torch.equal(cnt1.cpu(), ref_counts.cpu()):
+                raise RuntimeError("SingleHP and fused candidate counts differ")
+            line["singlehp"][lname] = {"ms_per_step": sh_ms, "value": points / (sh_ms * 1e-3),
+                                       "unit": "points/s", "fused_speedup": sh_ms / r["ms_per_step"],
+                                       "gbs": sb * points / (sh_ms * 1e-3) / 1e9}
+        log("singlehp: %s" % line["singlehp"])
         del out1, work1
 
     if not args.no_variants:
@@ -440,21 +589,30 @@ def main():
                          "storage": "%s of power x %g, fp32 sums" % (name, scale)}
             del store
         line["variants"] = var
+        log("variants done")
 
     if args.batched_fops > 0:
         del fop, ref_out
         torch.cuda.empty_cache()
         line["batched"] = batched_leg(args.batched_fops, max(3, args.steps // 40),
                                       2, dev)
+        log("batched: %.3f ms" % line["batched"]["ms_per_step"])
         fop = synth.make_ska(device=dev)
 
     if args.diff_fops > 0:
         line["differentiation"] = diff_leg(args.diff_fops, 3, 1, dev)
+        log("differentiation done")
+        torch.cuda.empty_cache()
+
+    if args.precision_fops > 0:
+        line["precision"] = precision_leg(args.precision_fops, dev, host_threads())
+        log("precision done")
         torch.cuda.empty_cache()
 
     if not args.no_cpu:
         fop_cpu = fop[:, :args.cpu_bins].cpu()
         line["cpu_baseline"] = cpu_baseline(fop_cpu, H, ta_np, args.cpu_bins)
+        log("cpu baseline done")
     print(json.dumps(line), flush=True)
 
 

@@ -54,7 +54,7 @@ def load_library(path):
     I64 = ctypes.c_int64
     I = ctypes.c_int
     lib.hso_sum_f32.argtypes = [P, I64, I64, I64, I, P]
-    lib.hso_sum_f64.argtypes = [P, I64, I64, I64, I, P]
+    lib.hso_sum_f64.argtypes = [P, I64, I64, I64, I, P, I]
     lib.hso_detect_f32.argtypes = [P, I64, I64, I64, I, P, ctypes.c_float, P, P, I64, P, I]
     lib.hso_vjp_f64.argtypes = [P, I64, I64, I, P]
     lib.hso_touch_counts.argtypes = [I64, I64, I, ctypes.c_uint32, P]
@@ -104,12 +104,13 @@ def sum_f32(fop, H, n_chan=None):
     return hp
 
 
-def sum_f64(fop, H, n_chan=None):
-    """All H planes [H][T][N] in fp64 from an fp64 copy of the input."""
+def sum_f64(fop, H, n_chan=None, nthreads=1):
+    """All H planes [H][T][N] in fp64 from an fp64 copy of the input
+    (nthreads: OpenMP threads over rows; the result does not depend on it)."""
     fop = np.ascontiguousarray(fop, dtype=np.float64)
     T, N, ld = _plane_args(fop, n_chan)
     hp = np.empty((H, T, N), dtype=np.float64)
-    rc = _load().hso_sum_f64(_ptr(fop), T, N, ld, H, _ptr(hp))
+    rc = _load().hso_sum_f64(_ptr(fop), T, N, ld, H, _ptr(hp), int(nthreads))
     if rc != 0:
         raise ValueError("hso_sum_f64 rc=%d" % rc)
     return hp

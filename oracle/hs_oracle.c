@@ -106,13 +106,22 @@ int hso_sum_f32(const float* fop, int64_t T, int64_t N, int64_t ld, int H, float
     return 0;
 }
 
-/* Same planes in fp64 from fp64 input (accuracy truth). */
-int hso_sum_f64(const double* fop, int64_t T, int64_t N, int64_t ld, int H, double* hp)
+/* Same planes in fp64 from fp64 input (accuracy truth).  Rows are
+ * independent within a plane: nthreads OpenMP threads share them. */
+int hso_sum_f64(const double* fop, int64_t T, int64_t N, int64_t ld, int H, double* hp, int nthreads)
 {
     if (T < 1 || N < 1 || H < 1 || ld < N) return -1;
+#ifdef _OPENMP
+    if (nthreads < 1) nthreads = 1;
+#else
+    (void)nthreads;
+#endif
     for (int k = 1; k <= H; k++) {
         double* cur = hp + (int64_t)(k - 1) * T * N;
         const double* prev = hp + (int64_t)(k - 2) * T * N;
+#ifdef _OPENMP
+#pragma omp parallel for schedule(dynamic, 1) num_threads(nthreads)
+#endif
         for (int64_t r = 0; r < T; r++) {
             int64_t rs = src_row(r, k, T);
             for (int64_t j = 0; j < N; j++) {

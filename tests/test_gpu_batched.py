@@ -189,3 +189,26 @@ def test_capture_on_fresh_plan_is_rejected():
             g1.replay()
             torch.cuda.synchronize()
             assert torch.equal(c1, ec)
+
+
+def test_batched_real_lengths_h16():
+    """One FOP each of 2^19, 2^20 and 2^21 bins (the batched workload's
+    lengths; the candidate word takes its bin field from the longest) in one
+    batched call with 16 planes: every candidate word and power bitwise equal
+    to the oracle's, FOP by FOP."""
+    H, T = 16, 85
+    lens = [1 << 19, 1 << 21, 1 << 20]
+    print("case batched real lengths", flush=True)
+    devs, stores = make_batch(lens, T, H, 9100)
+    ta = synth.thresholds(H, T)
+    plan = hs.Plan(T, 0, H, n_chans=lens)
+    caps = [1 << 21] * len(lens)
+    (_, _, _, out, _, _, counts), offs = batched_call(plan, devs, ta, caps)
+    res = unpack_batched(out, counts, offs, caps)
+    s_row, s_bin = plan.info["s_row"], plan.info["s_bin"]
+    for f, n in enumerate(lens):
+        gi, gp, gc = res[f]
+        want, wc = oracle_triples(stores[f], H, ta)
+        assert np.array_equal(gc, wc), (f, gc, wc)
+        assert gc[-1] > 10000
+        assert np.array_equal(triples(gi, gp, s_row, s_bin), want), f
