@@ -387,11 +387,11 @@ def diff_leg(n_fops, steps, warmup, dev):
     points = n_fops * T * N
     total = out["forward_ms"] + out["backward_ms"]
     # per-point bytes: the fused forward reads the FOP once (4); the
-    # backward reads the FOP (4), writes the H weight planes formed in the
-    # tile kernel (4H), reads them in the transpose (4H) and writes the
-    # gradient (4); the transpose's tile partials (about 0.6 of a plane) are
-    # not counted
-    fb, bb = 4, 8 + 8 * H
+    # backward reads the FOP (4, forming the weights in the tile pass),
+    # writes G_1 into the gradient (4), and the second pass reads and writes
+    # the gradient (8); the tile partials written and read back (about 0.6
+    # of a plane each way) are not counted
+    fb, bb = 4, 16
     out.update({"n_fops": n_fops, "points": points, "value": points / (total * 1e-3),
                 "unit": "points/s (forward + backward)",
                 "forward_gbs": fb * points / (out["forward_ms"] * 1e-3) / 1e9,

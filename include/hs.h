@@ -284,10 +284,10 @@ hs_status hs_sum_backward(const hs_plan* plan, const float* g, float* dfop, void
  * with g times the gradient of L = sum_k tau * lse[k-1] with respect to the
  * FOP (unscaled units), g = *gscale (fp64, device; NULL means 1), so that an
  * autograd engine can pass the upstream gradient without a host copy: the
- * weights exp(HP_k / tau - lse[k-1]) taken through hs_sum_backward; it
- * materialises the weights in `work` (fp32 plans form them inside the tile
- * kernel; other storage types store the planes and turn them into weights in
- * a second pass).  `work` must hold hs_lse_workspace_bytes(plan) bytes.
+ * weights exp(HP_k / tau - lse[k-1]) taken through the transpose of
+ * hs_sum_backward, formed inside its tile pass from the FOP (no weight plane
+ * is stored), then the tile partials added in a fixed order
+ * (deterministic).  `work` must hold hs_lse_workspace_bytes(plan) bytes.
  * Single-FOP plans only. */
 size_t hs_lse_workspace_bytes(const hs_plan* plan);
 hs_status hs_lse_forward(const hs_plan* plan, const void* fop, int64_t ld, float tau, double* lse,

@@ -818,15 +818,18 @@ hs_status hs_sum_backward(const hs_plan* p, const float* g, float* dfop, void* w
     }
 }
 
-// Workspace of the statistic: the H planes, then the larger of the backward
-// partials and the reduction's per-block pairs; at least the fused forward's
-// per-block pairs.
+// Workspace of the statistic: the backward's tile partials (tiles of
+// lse_backward_tile_rows() rows) and the fused forward's per-block pairs;
+// for 16-bit plans also the H planes the forward materialises, followed by
+// the larger of the partials and the plane reduction's pairs.
 size_t hs_lse_workspace_bytes(const hs_plan* p)
 {
     if (!p || p->n_fops != 0) return 0;
-    const size_t tail = std::max(partial_bytes(p), (size_t)hsk::lse_part_bytes(p->H));
+    const size_t bwd = (size_t)hsk::backward_partial_floats((int)p->T, p->H, hsk::lse_backward_tile_rows(), p->N) * 4;
     const size_t fused = (size_t)hsk::kLseMaxBlocks * p->H * 2 * sizeof(float);
-    return std::max(round256(plane_bytes(p) * p->H) + round256(tail), round256(fused));
+    if (p->dtype == HS_DTYPE_F32) return std::max(round256(bwd), round256(fused));
+    const size_t tail = std::max(bwd, (size_t)hsk::lse_part_bytes(p->H));
+    return round256(plane_bytes(p) * p->H) + round256(tail);
 }
 
 namespace {
@@ -916,32 +919,11 @@ hs_status hs_lse_backward(const hs_plan* p, const void* fop, int64_t ld, const d
     if (p->mapping != HS_MAP_PAPER) return HS_ERR_UNSUPPORTED;
     if (!fop_ok(p, fop, ld, p->N)) return HS_ERR_INVALID;
     try {
-        hipStream_t s = (hipStream_t)stream;
-        DevTabs t;
-        const hs_status st = device_tables(p, s, &t);
-        if (st != HS_OK) return st;
-        float* planes = static_cast<float*>(work);
-        float* part = reinterpret_cast<float*>(static_cast<char*>(work) + round256(plane_bytes(p) * p->H));
-        hsk::TileArgs a = tile_args(p, fop, ld, t);
-        a.hp = planes;
-        hipError_t e;
-        if (p->dtype == HS_DTYPE_F32) {
-            // the weights straight from the tile kernel (the same fp64
-            // difference and expf as the separate pass below)
-            a.lse = lse;
-            a.inv_tau = 1.0 / (double)tau;
-            a.gscale = gscale;
-            e = hsk::launch_fused(hsk::kModeWeights, p->dtype, p->H, a, p->tiles_total,
-                                  persistent_grid(p, p->tiles_total), p->lds_bytes, s);
-            if (e != hipSuccess) return HS_ERR_HIP;
-        } else {
-            e = hsk::launch_fused(hsk::kModeSum, p->dtype, p->H, a, p->tiles_total,
-                                  persistent_grid(p, p->tiles_total), p->lds_bytes, s);
-            if (e != hipSuccess) return HS_ERR_HIP;
-            e = hsk::launch_lse_weights(planes, p->T * p->N, p->H, tau, lse, gscale, s);
-            if (e != hipSuccess) return HS_ERR_HIP;
-        }
-        return from_hip(hsk::launch_backward(planes, dfop, part, (int)p->T, p->N, p->H, p->tile_rows, s));
+        // the weights are formed inside the transpose's tile pass: no weight
+        // plane is written or read back
+        return from_hip(hsk::launch_lse_backward_fused(p->dtype, fop, ld, (int)p->T, p->N, p->H, 1.0f / p->scale,
+                                                       (double)tau, lse, gscale, dfop, static_cast<float*>(work),
+                                                       (hipStream_t)stream));
     } catch (...) {
         return HS_ERR_HIP;
     }

@@ -129,7 +129,7 @@ hipError_t launch_fused(int mode, int dtype, int H, const TileArgs& a, int64_t n
                         int lds_bytes, hipStream_t s)
 {
     if (H < 1 || H > kMaxH) return hipErrorInvalidValue;
-    if (mode == kModeLse || mode == kModeWeights) {
+    if (mode == kModeLse) {
         if (dtype != HS_DTYPE_F32) return hipErrorInvalidValue;
 #define HS_CALL(g) launch_stat_f32_g##g(mode, H, a, n_tiles, grid, lds_bytes, s)
         HS_GROUP_CASES(HS_CALL)

@@ -1,4 +1,4 @@
-// Statistic modes (fused log-sum-exp, softmax weights) for fp32 FOP storage,
+// The fused log-sum-exp statistic for fp32 FOP storage,
 // H = 9..12.
 #define HS_INST_T float
 #define HS_INST_NAME f32

@@ -657,12 +657,6 @@ __device__ __forceinline__ void compute_tile(const TileArgs& a, const RowGeo& g,
                 float o[kV];
 #pragma unroll
                 for (int v = 0; v < kV; ++v) o[v] = Scaled<TIn>::value ? acc[v] * a.inv_scale : acc[v];
-                if constexpr (MODE == kModeWeights) {
-                    const double lk = a.lse[k - 1];
-                    const float gsc = a.gscale ? (float)*a.gscale : 1.0f;
-#pragma unroll
-                    for (int v = 0; v < kV; ++v) o[v] = gsc * expf((float)((double)o[v] * a.inv_tau - lk));
-                }
                 if (FULL && (N & 3) == 0) {
                     *reinterpret_cast<float4*>(dst) = make_float4(o[0], o[1], o[2], o[3]);
                 } else {
@@ -1053,19 +1047,13 @@ static hipError_t launch_fused_t(int mode, const TileArgs& a, int64_t n_tiles, i
     return hipGetLastError();
 }
 
-// The statistic's modes (fp32 storage only; their own translation units).
+// The statistic's mode (fp32 storage only; its own translation units).
 template <int H>
 static hipError_t launch_stat_t(int mode, const TileArgs& a, int64_t n_tiles, int grid, int lds_bytes,
                                 hipStream_t s)
 {
     TileArgs b = a;
-    if (mode == kModeWeights) {
-        auto k = k_fused<float, H, kModeWeights>;
-        (void)hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, lds_bytes);
-        const int g = resident_grid(k, lds_bytes, n_tiles, grid);
-        if (g < 8) b.sched = nullptr;
-        hipLaunchKernelGGL(k, dim3(g), dim3(kThreads), lds_bytes, s, b, n_tiles);
-    } else if (mode == kModeLse) {
+    if (mode == kModeLse) {
         // the caller fixes the grid (one partial pair per block)
         auto k = k_fused<float, H, kModeLse>;
         if (grid < 1 || grid > kLseMaxBlocks || grid > n_tiles) return hipErrorInvalidValue;

@@ -21,6 +21,8 @@
 // |lse| is large.
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "hs_internal.h"
 
 namespace hsk {
@@ -173,6 +175,200 @@ __global__ __launch_bounds__(256) void k_bwd_reduce(float* __restrict__ dfop, co
     }
 }
 
+// ---- statistic backward, weights formed in the transpose's tile pass -------
+//
+// dL/dFOP for L = sum_k tau lse_k is the transpose applied to the weights
+// g_k = gscale exp(HP_k / tau - lse_k).  Instead of writing the H weight
+// planes and reading them back, the tile pass forms them: each thread takes
+// one row and four bins of a 16-row x 256-bin tile, sums HP_1..HP_H from the
+// FOP in the order of Eq. 2 (the forward's sums, so the weights are those of
+// the planes the statistic was taken over), turns each into its weight in
+// registers, forms the suffix sums G_m, writes G_1 to dFOP, and for m >= 2
+// sums each target's m x m box inside the tile into the per-(m, tile)
+// partial rectangles that the second pass adds (the same deterministic
+// layout and order as the plain transpose above).
+template <int A, int B, typename F>
+__host__ __device__ inline void static_for(F&& f)
+{
+    if constexpr (A <= B) {
+        f(std::integral_constant<int, A>{});
+        static_for<A + 1, B>(f);
+    }
+}
+
+constexpr int kFR = 16;                     // rows per tile: one wave each
+constexpr int kFThreads = kFR * kLanes;     // 1024
+
+template <typename TIn> struct GIo;
+template <> struct GIo<float> {
+    __device__ static float ld(const void* p, int64_t e) { return static_cast<const float*>(p)[e]; }
+};
+template <> struct GIo<_Float16> {
+    __device__ static float ld(const void* p, int64_t e) { return (float)static_cast<const _Float16*>(p)[e]; }
+};
+struct bf16_bits {
+    uint16_t b;
+};
+template <> struct GIo<bf16_bits> {
+    __device__ static float ld(const void* p, int64_t e)
+    {
+        return __uint_as_float((uint32_t)static_cast<const uint16_t*>(p)[e] << 16);
+    }
+};
+
+template <typename TIn, int H>
+__global__ __launch_bounds__(kFThreads) void k_lse_bwd_tiles(const void* __restrict__ fop, int64_t ld, int T, int N,
+                                                             float inv_scale, double inv_tau,
+                                                             const double* __restrict__ lse,
+                                                             const double* __restrict__ gscale_p,
+                                                             float* __restrict__ dfop, float* __restrict__ part,
+                                                             int row_blocks, int n_bt)
+{
+    __shared__ float tile[kFR * kTileBins];
+    __shared__ float hrow[kFR * stage_pitch(2)];     // row sums over each target's bins
+    const int rb = blockIdx.x / n_bt;
+    const int bt = blockIdx.x - rb * n_bt;
+    const int r0 = rb * kFR;
+    const int nr = min(kFR, T - r0);
+    const int j0 = bt * kTileBins;
+    const int nb = min(kTileBins, N - j0);
+    const int c = T / 2;
+    const int lane = threadIdx.x & 63;
+    const int rr = threadIdx.x >> 6;            // row of the tile (the wave)
+    const int r = r0 + rr;
+    const bool row_ok = rr < nr;
+    const float gsc = gscale_p ? (float)*gscale_p : 1.0f;
+
+    // weights of every plane at the thread's four points (0 outside the plane)
+    float G[H][kV];
+    {
+        // every source value first (unconditional loads at clamped indices,
+        // so that all of them are in flight together), then the sums
+#pragma unroll
+        for (int k = 1; k <= H; ++k) {
+            const int sr = row_ok ? floordiv32(r - c, k) + c : 0;
+#pragma unroll
+            for (int v = 0; v < kV; ++v) {
+                const int jj = kV * lane + v < nb ? j0 + kV * lane + v : j0;
+                G[k - 1][v] = GIo<TIn>::ld(fop, (int64_t)sr * ld + jj / k);
+            }
+        }
+        float acc[kV];
+#pragma unroll
+        for (int k = 1; k <= H; ++k) {
+#pragma unroll
+            for (int v = 0; v < kV; ++v) {
+                const bool ok = row_ok && kV * lane + v < nb;
+                const float x = G[k - 1][v];
+                acc[v] = k == 1 ? x : acc[v] + x;
+                const float hp = acc[v] * inv_scale;
+                // the exponent HP/tau - lse in fp64 (both terms can be large),
+                // then exp through the hardware exp2 on the fp32 difference
+                const float d = (float)((double)hp * inv_tau - lse[k - 1]);
+                G[k - 1][v] = ok ? gsc * __builtin_amdgcn_exp2f(d * 1.4426950408889634f) : 0.0f;
+            }
+        }
+    }
+    // suffix sums G_m = g_m + G_{m+1}, from the last plane down
+#pragma unroll
+    for (int m = H - 1; m >= 1; --m) {
+#pragma unroll
+        for (int v = 0; v < kV; ++v) G[m - 1][v] = G[m - 1][v] + G[m][v];
+    }
+    if (row_ok) {
+        float* dst = dfop + (int64_t)r * N + j0;
+#pragma unroll
+        for (int v = 0; v < kV; ++v)
+            if (kV * lane + v < nb) dst[kV * lane + v] = G[0][v];
+    }
+    // box sums of G_m, m >= 2, inside the tile: first each row's sums over
+    // the m bins of every target column, then each target's sum over its m
+    // rows (m is a compile-time constant here: the short loops unroll)
+    static_for<2, H>([&](auto mc) {
+        constexpr int m = decltype(mc)::value;
+        constexpr int NR = stage_rows(m), P = stage_pitch(m);
+        __syncthreads();               // the previous factor's sums are done
+#pragma unroll
+        for (int v = 0; v < kV; ++v) tile[rr * kTileBins + kV * lane + v] = G[m - 1][v];
+        __syncthreads();
+        const int blo = j0 / m;
+        for (int e = threadIdx.x; e < nr * P; e += kFThreads) {
+            const int rw = e / P, tc = e - rw * P;
+            const int jbase = m * (blo + tc) - j0;
+            float acc = 0.0f;
+#pragma unroll
+            for (int dc = 0; dc < m; ++dc) {
+                const int j = jbase + dc;
+                if (j >= 0 && j < nb) acc += tile[rw * kTileBins + j];
+            }
+            hrow[rw * P + tc] = acc;
+        }
+        __syncthreads();
+        const int lo = src_row(r0, m, c);
+        float* out = part + partial_offset(m, row_blocks, n_bt) + (((int64_t)rb * NR) * n_bt + bt) * P;
+        for (int e = threadIdx.x; e < NR * P; e += kFThreads) {
+            const int tr = e / P, tc = e - tr * P;
+            const int rbase = c + m * (lo + tr - c) - r0;
+            float acc = 0.0f;
+#pragma unroll
+            for (int dr = 0; dr < m; ++dr) {
+                const int rw = rbase + dr;
+                if (rw >= 0 && rw < nr) acc += hrow[rw * P + tc];
+            }
+            out[(int64_t)tr * n_bt * P + tc] = acc;
+        }
+    });
+}
+
+// Second pass of the statistic's backward: dFOP(a, b) += the tile partials
+// covering (a, b) for m = 2..H (m and the tile height are compile-time
+// constants).  Only points that some m >= 2 box maps to are touched: bins
+// b <= (N - 1) / 2 of rows whose boxes meet the plane; each thread takes
+// four consecutive bins of one row.
+template <int H, int R>
+__global__ __launch_bounds__(256) void k_bwd_reduce_t(float* __restrict__ dfop, const float* __restrict__ part, int T,
+                                                      int N, int row_blocks, int n_bt)
+{
+    const int c = T / 2;
+    const int half = (N - 1) / 2 + 1;             // bins with an m = 2 box
+    const int nq = (half + 3) / 4;
+    const int64_t total = (int64_t)T * nq;
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        const int a = (int)(e / nq);
+        const int b0 = (int)(e - (int64_t)a * nq) * 4;
+        float add[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+        bool any = false;
+        static_for<2, H>([&](auto mc) {
+            constexpr int m = decltype(mc)::value;
+            constexpr int NR = stage_rows(m), P = stage_pitch(m);
+            const int first = max(c + m * (a - c), 0), last = min(c + m * (a - c) + m - 1, T - 1);
+            if (first > last) return;
+            const float* pm = part + partial_offset(m, row_blocks, n_bt);
+            for (int rb = first / R; rb <= last / R; ++rb) {
+                const int tr = a - src_row(rb * R, m, c);
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int b = b0 + v;
+                    if ((int64_t)m * b > N - 1) continue;
+                    const int jb0 = m * b, jb1 = min(m * b + m - 1, N - 1);
+                    for (int bt = jb0 / kTileBins; bt <= jb1 / kTileBins; ++bt) {
+                        const int tc = b - (bt * kTileBins) / m;
+                        add[v] += pm[(((int64_t)rb * NR + tr) * n_bt + bt) * P + tc];
+                        any = true;
+                    }
+                }
+            }
+        });
+        if (any) {
+            float* d = dfop + (int64_t)a * N + b0;
+#pragma unroll
+            for (int v = 0; v < 4; ++v)
+                if (b0 + v < half) d[v] = d[v] + add[v];
+        }
+    }
+}
+
 // Log-sum-exp, level 1: block (k, i) reduces a contiguous chunk of plane k
 // to a (max, sum of exp(x - max)) pair, x = HP / tau evaluated in fp64.
 constexpr int kLseBlocks = 256;
@@ -284,22 +480,6 @@ __global__ __launch_bounds__(kLseFinalThreads) void k_lse_fused_final(const floa
     if (threadIdx.x == 0) lse[k] = M * cd + log(red[0]);
 }
 
-// Weights of L = sum_k tau * lse_k: dL/dHP_k = exp(HP_k / tau - lse_k), times
-// the upstream gradient *gscale (1 when null).
-__global__ __launch_bounds__(256) void k_lse_weights(float* __restrict__ hp, int64_t plane, int H, double inv_tau,
-                                                     const double* __restrict__ lse,
-                                                     const double* __restrict__ gscale_p)
-{
-    const float gscale = gscale_p ? (float)*gscale_p : 1.0f;
-    const int64_t total = plane * H;
-    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
-         e += (int64_t)gridDim.x * blockDim.x) {
-        const int k = (int)(e / plane);
-        const double d = (double)hp[e] * inv_tau - lse[k];
-        hp[e] = gscale * expf((float)d);
-    }
-}
-
 int grid_for(int64_t n, int threads, int cap)
 {
     const int64_t b = (n + threads - 1) / threads;
@@ -331,6 +511,53 @@ hipError_t launch_backward(const float* g, float* dfop, float* part, int T, int6
     return hipGetLastError();
 }
 
+hipError_t launch_lse_backward_fused(int dtype, const void* fop, int64_t ld, int T, int64_t N, int H, float inv_scale,
+                                    double tau, const double* lse, const double* gscale, float* dfop, float* part,
+                                    hipStream_t s)
+{
+    const int row_blocks = (T + kFR - 1) / kFR;
+    const int n_bt = (int)((N + kTileBins - 1) / kTileBins);
+    const int64_t tiles = (int64_t)row_blocks * n_bt;
+    if (tiles > 0x7fffffff || H < 1 || H > kMaxH) return hipErrorInvalidValue;
+    const dim3 g((unsigned)tiles), b(kFThreads);
+    const double it = 1.0 / tau;
+    bool ok = false;
+    static_for<1, kMaxH>([&](auto hc) {
+        constexpr int HH = decltype(hc)::value;
+        if (HH != H) return;
+        ok = true;
+        switch (dtype) {
+        case HS_DTYPE_F32:
+            hipLaunchKernelGGL((k_lse_bwd_tiles<float, HH>), g, b, 0, s, fop, ld, T, (int)N, inv_scale, it, lse,
+                               gscale, dfop, part, row_blocks, n_bt);
+            break;
+        case HS_DTYPE_F16:
+            hipLaunchKernelGGL((k_lse_bwd_tiles<_Float16, HH>), g, b, 0, s, fop, ld, T, (int)N, inv_scale, it, lse,
+                               gscale, dfop, part, row_blocks, n_bt);
+            break;
+        case HS_DTYPE_BF16:
+            hipLaunchKernelGGL((k_lse_bwd_tiles<bf16_bits, HH>), g, b, 0, s, fop, ld, T, (int)N, inv_scale, it,
+                               lse, gscale, dfop, part, row_blocks, n_bt);
+            break;
+        default:
+            ok = false;
+        }
+    });
+    if (!ok) return hipErrorInvalidValue;
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const int64_t quads = (int64_t)T * (((N - 1) / 2 + 1 + 3) / 4);
+    static_for<2, kMaxH>([&](auto hc) {
+        constexpr int HH = decltype(hc)::value;
+        if (HH == H)
+            hipLaunchKernelGGL((k_bwd_reduce_t<HH, kFR>), dim3(grid_for(quads, 256, 65536)), dim3(256), 0, s, dfop,
+                               part, T, (int)N, row_blocks, n_bt);
+    });
+    return hipGetLastError();
+}
+
+int lse_backward_tile_rows() { return kFR; }
+
 int64_t lse_part_bytes(int H) { return (int64_t)H * kLseBlocks * (8 + 4); }
 
 hipError_t launch_lse_reduce(const float* hp, int64_t plane, int H, double tau, void* work, double* lse,
@@ -358,12 +585,5 @@ hipError_t launch_lse_loss(const double* lse, int H, double tau, double* loss, h
     return hipGetLastError();
 }
 
-hipError_t launch_lse_weights(float* hp, int64_t plane, int H, double tau, const double* lse, const double* gscale,
-                              hipStream_t s)
-{
-    hipLaunchKernelGGL(k_lse_weights, dim3(grid_for(plane * H, 256, 65536)), dim3(256), 0, s, hp, plane, H,
-                       1.0 / tau, lse, gscale);
-    return hipGetLastError();
-}
 
 }  // namespace hsk

@@ -199,11 +199,6 @@ struct TileArgs {
     // exp2((x - max) * lse_c)) of the block's values x in storage units
     float* lse_part;        // [gridDim.x][H][2]
     float lse_c;            // inv_scale * log2(e) / tau
-    // softmax weights of the statistic, written to hp in place of the planes:
-    // gscale * exp(HP_k / tau - lse[k-1])
-    const double* lse;      // [H] device
-    double inv_tau;
-    const double* gscale;         // upstream gradient (device, null: 1)
 };
 
 // Arguments of the batched persistent launch.
@@ -253,7 +248,7 @@ struct WalkArgs {
     const uint32_t* xseg;         // [9]: segments of XCD x are [xseg[x], xseg[x+1])
 };
 
-enum Mode { kModeDetect = 0, kModeSum = 1, kModeLse = 2, kModeWeights = 3 };
+enum Mode { kModeDetect = 0, kModeSum = 1, kModeLse = 2 };
 
 // Fused log-sum-exp: most blocks one launch may use (the partial pairs of
 // the workspace are sized for it).
@@ -321,6 +316,13 @@ hipError_t launch_walk(int dtype, int H, const WalkArgs& a, int grid, int lds_by
 
 // Transpose of the plane map and the log-sum-exp statistic (hs_grad.hip).
 int64_t backward_partial_floats(int T, int H, int R, int64_t N);
+// The statistic's backward with the weights formed in the transpose's tile
+// pass (tiles of lse_backward_tile_rows() rows; `part` holds
+// backward_partial_floats(T, H, that, N) floats).
+hipError_t launch_lse_backward_fused(int dtype, const void* fop, int64_t ld, int T, int64_t N, int H, float inv_scale,
+                                    double tau, const double* lse, const double* gscale, float* dfop, float* part,
+                                    hipStream_t s);
+int lse_backward_tile_rows();
 hipError_t launch_backward(const float* g, float* dfop, float* part, int T, int64_t N, int H, int R,
                            hipStream_t s);
 int64_t lse_part_bytes(int H);
@@ -329,9 +331,6 @@ hipError_t launch_lse_reduce(const float* hp, int64_t plane, int H, double tau, 
 hipError_t launch_lse_fused_final(const float* part, int nblk, int H, double inv_scale, double tau,
                                   double* lse, hipStream_t s);
 hipError_t launch_lse_loss(const double* lse, int H, double tau, double* loss, hipStream_t s);
-hipError_t launch_lse_weights(float* hp, int64_t plane, int H, double tau, const double* lse, const double* gscale,
-                              hipStream_t s);
-
 // Canonical candidate order (hs_sort.hip).
 hipError_t sort_workspace(int64_t n, size_t* bytes);
 hipError_t sort_candidates(uint64_t* cand, int64_t n, void* work, hipStream_t s);

@@ -200,16 +200,43 @@ def test_lse_fused_grids(blocks):
 
 @pytest.mark.parametrize("name,dtype", [("f16", torch.float16), ("bf16", torch.bfloat16)])
 def test_lse_reduced_precision_storage(name, dtype):
-    """16-bit storage takes the materialising path: lse of the planes of the
-    stored values (unscaled) against the oracle on the same values."""
+    """16-bit storage: lse (through materialised planes) and its gradient
+    (fused) of the stored values, unscaled, against the oracle on the same
+    values."""
     T, N, H, tau, scale = 21, 3000, 8, 0.7, 0.125
     x = synth.noise(T, N, 44)
     store = synth.quantize(x, dtype, scale)
     plan = hs.Plan(T, N, H, dtype=name, input_scale=scale)
-    got = plan.lse(store.cuda(), tau).cpu().numpy()
+    dev = store.cuda()
+    lse = plan.lse(dev, tau)
+    got = lse.cpu().numpy()
     S = oracle.sum_f32(store.to(torch.float32).numpy(), H) / scale
     ref = olse.lse_f64(S, tau)
     assert np.all(np.abs(got - ref) <= lse_tol(T, N, ref)), (got - ref)
+    # the gradient (weights formed in the transpose's tile pass from the
+    # 16-bit FOP), in unscaled units, against the oracle's on the same sums
+    dfop = plan.lse_backward(dev, lse, tau, gscale=1.25).cpu().numpy().astype(np.float64)
+    want = olse.grad_fop_f64(S, tau, gscale=1.25)
+    assert np.all(np.abs(dfop - want) <= 1e-5 * np.abs(want) + 1e-8 * np.abs(want).max())
+
+
+def test_lse_backward_deterministic_ragged():
+    """The statistic's gradient on a plane whose rows and bins leave ragged
+    tiles (85 rows over 16-row tiles, bins not a multiple of 256), 16 planes:
+    within the bound of the oracle, and bitwise the same on a second call."""
+    T, N, H, tau = 85, 256 * 9 + 76, 16, 0.9
+    x = synth.noise(T, N, 71)
+    synth.inject(x, [(1, 23, 25.0, H)])
+    plan = hs.Plan(T, N, H)
+    dev = x.cuda()
+    lse = plan.lse(dev, tau)
+    a = plan.lse_backward(dev, lse, tau)
+    b = plan.lse_backward(dev, lse, tau)
+    assert torch.equal(a, b)
+    S = oracle.sum_f32(x.numpy(), H)
+    want = olse.grad_fop_f64(S, tau)
+    got = a.cpu().numpy().astype(np.float64)
+    assert np.all(np.abs(got - want) <= 1e-5 * np.abs(want) + 1e-8 * np.abs(want).max())
 
 
 def test_backward_unaligned_cotangent():
