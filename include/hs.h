@@ -106,6 +106,8 @@ typedef struct hs_plan_desc {
                                /* of at most 16 KB; otherwise the tile kernel    */
                                /* runs.  Results do not depend on it.            */
     int32_t mapping;           /* hs_mapping (0 = HS_MAP_PAPER)                  */
+    int32_t bins_per_lane;     /* tuning: bins per lane V of the strip walk (2,  */
+                               /* 4 or 8: strips of 64 V bins); 0 = planner (4)  */
 } hs_plan_desc;
 
 /* Geometry chosen by the planner (host values; no GPU needed). */
@@ -125,11 +127,12 @@ typedef struct hs_plan_info {
     int32_t detector;           /* detection kernel: 0 tile kernel, 1 strip      */
                                 /* walk, 2 fractional-mapping kernel             */
     int32_t mapping;            /* hs_mapping of the plan                        */
+    int32_t bins_per_lane;      /* strip walk: bins per lane (0: no walk)        */
 } hs_plan_info;
 
 /* Create a plan.  Validates the shapes (HS_ERR_INVALID: N_temp < 1, n_hp
- * outside 1..16, unknown dtype or mapping, input_scale not a power of
- * two, n_fops outside 0..65535, a batch with the fractional mapping,
+ * outside 1..16, unknown dtype or mapping, bins_per_lane not 0, 2, 4 or
+ * 8, input_scale not a power of two, n_fops outside 0..65535, a batch with the fractional mapping,
  * a bin count < 1, or a candidate word wider than 32 bits, i.e.
  * ceil(log2 N_temp) + ceil(log2 N_hp) + ceil(log2 N_chan) > 32).  Host only:
  * touches no GPU. */

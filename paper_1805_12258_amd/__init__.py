@@ -48,7 +48,8 @@ class hs_plan_desc(ctypes.Structure):
                 ("dtype", ctypes.c_int32), ("input_scale", ctypes.c_float),
                 ("n_fops", ctypes.c_int32), ("n_chans", ctypes.POINTER(ctypes.c_int64)),
                 ("tile_rows", ctypes.c_int32), ("persistent_blocks", ctypes.c_int32),
-                ("schedule", ctypes.c_int32), ("mapping", ctypes.c_int32)]
+                ("schedule", ctypes.c_int32), ("mapping", ctypes.c_int32),
+                ("bins_per_lane", ctypes.c_int32)]
 
 
 class hs_plan_info(ctypes.Structure):
@@ -59,7 +60,7 @@ class hs_plan_info(ctypes.Structure):
                 ("row_blocks", ctypes.c_int32), ("lds_bytes", ctypes.c_int32),
                 ("tiles_total", ctypes.c_int64), ("src_rows", ctypes.c_int32 * 17),
                 ("staged_words", ctypes.c_int64), ("detector", ctypes.c_int32),
-                ("mapping", ctypes.c_int32)]
+                ("mapping", ctypes.c_int32), ("bins_per_lane", ctypes.c_int32)]
 
 
 _P = ctypes.c_void_p
@@ -136,7 +137,7 @@ _MAPPINGS = {"paper": HS_MAP_PAPER, "fractional": HS_MAP_FRACTIONAL}
 
 
 def hs_plan_create(n_temp, n_chan=0, n_hp=8, dtype="f32", input_scale=1.0, n_chans=None,
-                   tile_rows=0, persistent_blocks=0, schedule=0, mapping="paper"):
+                   tile_rows=0, persistent_blocks=0, schedule=0, mapping="paper", bins_per_lane=0):
     """Create a plan (host only).  Returns an opaque handle (ctypes.c_void_p)."""
     d = hs_plan_desc()
     d.n_temp = int(n_temp)
@@ -153,6 +154,7 @@ def hs_plan_create(n_temp, n_chan=0, n_hp=8, dtype="f32", input_scale=1.0, n_cha
     d.persistent_blocks = int(persistent_blocks)
     d.schedule = int(schedule)
     d.mapping = _MAPPINGS[mapping] if isinstance(mapping, str) else int(mapping)
+    d.bins_per_lane = int(bins_per_lane)
     h = ctypes.c_void_p()
     _check(_c_hs_plan_create(ctypes.byref(h), ctypes.byref(d)), "hs_plan_create")
     return h
@@ -327,7 +329,7 @@ class Plan:
     """Owning wrapper of an hs_plan handle."""
 
     def __init__(self, n_temp, n_chan=0, n_hp=8, dtype="f32", input_scale=1.0, n_chans=None,
-                 tile_rows=0, persistent_blocks=0, schedule=0, mapping="paper"):
+                 tile_rows=0, persistent_blocks=0, schedule=0, mapping="paper", bins_per_lane=0):
         self.n_temp, self.n_hp = int(n_temp), int(n_hp)
         self.n_chan = int(n_chan or 0)
         self.n_chans = None if n_chans is None else [int(x) for x in n_chans]
@@ -338,7 +340,7 @@ class Plan:
         self.torch_dtype = {0: torch.float32, 1: torch.float16, 2: torch.bfloat16}.get(self.dtype)
         self.input_scale = float(input_scale)
         self.handle = hs_plan_create(n_temp, n_chan, n_hp, self.dtype, input_scale, n_chans,
-                                     tile_rows, persistent_blocks, schedule, mapping)
+                                     tile_rows, persistent_blocks, schedule, mapping, bins_per_lane)
         self.info = hs_plan_info_get(self.handle)
 
     def __del__(self):

@@ -2,10 +2,15 @@
 
 Every candidate configuration computes the same planes and candidate lists
 (the sums do not depend on the tiling or on the order tiles are visited), so
-tuning only changes speed.  Searched: rows per tile (`tile_rows`), the
-persistent grid size (`persistent_blocks`) and, for single-FOP plans, the
-tile order (`schedule`: XCD lists or contiguous chunks).  Bins per tile are
-fixed at compile time (256).
+tuning only changes speed.  Searched, after the planner's defaults:
+
+* the strip-walk detection kernel with V = 2, 4 or 8 bins per lane
+  (`bins_per_lane`; strips of B = 64 V = 128, 256 or 512 bins);
+* the tile kernel (256-bin tiles, 4 bins per lane) with 32, 24 or 16 rows
+  per tile (`tile_rows`);
+* for each, the resident grid or one block per compute unit
+  (`persistent_blocks`), and for single-FOP plans the XCD order or
+  increasing order of the units (`schedule`).
 
 The best configuration per (shape, planes, dtype, FOPs, device) is kept in a
 JSON cache; `tuned_plan` builds a plan from it, tuning first on a miss.
@@ -15,20 +20,39 @@ import os
 
 DEFAULT_CACHE = os.path.join(os.path.expanduser("~"), ".cache", "hs_autotune.json")
 
-TILE_ROWS = (0, 24, 16)                 # 0: the planner's choice (32)
+TILE_ROWS = (0, 24, 16)                 # tile kernel: 0 is the planner's choice (32)
+BINS_PER_LANE = (4, 2, 8)               # strip walk: strips of 64 V bins
 GRID_FACTORS = (0, 1)                   # 0: occupancy; else blocks per CU (resident grids only)
 MARGIN = 0.02                           # a candidate must beat the incumbent by 2 %
-SCHEDULES = (0, 1)
 
 
 def candidates(single_fop, cus=256):
-    """The configurations searched (dicts of Plan keyword arguments)."""
-    out = []
-    for r in TILE_ROWS:
-        for f in GRID_FACTORS:
-            for s in (SCHEDULES if single_fop else (0,)):
-                out.append({"tile_rows": r, "persistent_blocks": f * cus, "schedule": s})
+    """The configurations searched (dicts of Plan keyword arguments): the
+    planner's defaults first, then every walk and tile variant."""
+    out = [{"schedule": 0}]
+    orders = ((4, 1), (2, 3)) if single_fop else ((4,), (2,))   # (walk orders, tile orders)
+    for f in GRID_FACTORS:
+        for v in BINS_PER_LANE:
+            for s in orders[0]:
+                out.append({"schedule": s, "bins_per_lane": v, "persistent_blocks": f * cus})
+        for r in TILE_ROWS:
+            for s in orders[1]:
+                out.append({"schedule": s, "tile_rows": r, "persistent_blocks": f * cus})
     return out
+
+
+def summary(best, best_ms, tried):
+    """The choice and its margins: over the planner's defaults (the first
+    candidate) and over the runner-up."""
+    valid = sorted((t for t in tried if t["ms"] is not None), key=lambda t: t["ms"])
+    default_ms = tried[0]["ms"]
+    runner = next((t for t in valid if t["config"] != best), None)
+    return {"config": best, "ms": best_ms, "default_ms": default_ms,
+            "gain_vs_default": (default_ms / best_ms - 1.0) if default_ms else None,
+            "runner_up": runner["config"] if runner else None,
+            "runner_up_ms": runner["ms"] if runner else None,
+            "margin_vs_runner_up": (runner["ms"] / best_ms - 1.0) if runner else None,
+            "configs_tried": len(tried)}
 
 
 def cache_key(T, N, H, dtype, n_chans, device_name):

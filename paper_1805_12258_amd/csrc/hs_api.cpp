@@ -172,7 +172,8 @@ void build_walk(hs_plan* p, bool linear)
     };
     std::vector<int64_t> nchan;
     if (p->n_fops == 0) {
-        const auto lists = walk_strip_lists((p->N + hsk::kWalkStripBins - 1) / hsk::kWalkStripBins, 8, linear);
+        const int64_t sb = 64 * (int64_t)p->walk_v;
+        const auto lists = walk_strip_lists((p->N + sb - 1) / sb, 8, linear);
         for (int x = 0; x < 8; ++x) {
             xseg[x] = (uint32_t)(seg.size() / 4);
             const auto r = add_units(lists[x]);
@@ -189,7 +190,8 @@ void build_walk(hs_plan* p, bool linear)
             const int64_t n = p->n_chans[f];
             auto it = std::find_if(by_len.begin(), by_len.end(), [&](const auto& e) { return e.first == n; });
             if (it == by_len.end()) {
-                const auto lists = walk_strip_lists((n + hsk::kWalkStripBins - 1) / hsk::kWalkStripBins, 1, linear);
+                const int64_t sb = 64 * (int64_t)p->walk_v;
+                const auto lists = walk_strip_lists((n + sb - 1) / sb, 1, linear);
                 by_len.push_back({n, add_units(lists[0])});
                 it = by_len.end() - 1;
             }
@@ -234,7 +236,7 @@ void build_walk(hs_plan* p, bool linear)
     if (!seg.empty()) std::memcpy(p->walk_tab.data() + p->off_seg, seg.data(), seg.size() * 4);
     if (!nchan.empty()) std::memcpy(p->walk_tab.data() + p->off_nchan, nchan.data(), nchan.size() * 8);
     if (!ent.empty()) std::memcpy(p->walk_tab.data() + p->off_ent, ent.data(), ent.size() * 4);
-    p->walk_lds = hsk::walk_lds_bytes(T, p->H, p->dtype);
+    p->walk_lds = hsk::walk_lds_bytes(T, p->H, p->dtype, p->walk_v);
     p->walk = true;
 }
 
@@ -409,11 +411,13 @@ hs_status hs_plan_create(hs_plan** out, const hs_plan_desc* d)
         if (d->tile_rows < 0 || d->persistent_blocks < 0) return HS_ERR_INVALID;
         if (d->schedule < 0 || d->schedule > 4) return HS_ERR_INVALID;
         if (d->mapping != HS_MAP_PAPER && d->mapping != HS_MAP_FRACTIONAL) return HS_ERR_INVALID;
+        if (d->bins_per_lane != 0 && !hsk::walk_v_ok(d->bins_per_lane)) return HS_ERR_INVALID;
         if (d->mapping == HS_MAP_FRACTIONAL && (d->n_fops != 0 || d->n_chan > hsk::kFracMaxBins))
             return HS_ERR_INVALID;
 
         hs_plan* p = new hs_plan();
         p->mapping = d->mapping;
+        p->walk_v = d->bins_per_lane ? d->bins_per_lane : 4;
         p->T = d->n_temp;
         p->H = d->n_hp;
         p->dtype = d->dtype;
@@ -543,6 +547,7 @@ hs_status hs_plan_info_get(const hs_plan* p, hs_plan_info* info)
     info->tiles_total = p->tiles_total;
     info->detector = p->mapping == HS_MAP_FRACTIONAL ? 2 : (p->walk ? 1 : 0);
     info->mapping = p->mapping;
+    info->bins_per_lane = p->walk ? p->walk_v : 0;
     // distinct source rows of each stretch factor over the full column, and the
     // words one full-height tile at a 256-bin aligned position stages
     const int64_t c = p->T / 2;
@@ -609,7 +614,7 @@ hs_status hs_detect(const hs_plan* p, const void* fop, int64_t ld, const float* 
             a.out = out;
             a.cap = capacity;
             a.counts = reinterpret_cast<unsigned long long*>(counts);
-            if (hsk::launch_walk(p->dtype, p->H, a, p->persistent_blocks, p->walk_lds, s) != hipSuccess)
+            if (hsk::launch_walk(p->dtype, p->H, p->walk_v, a, p->persistent_blocks, p->walk_lds, s) != hipSuccess)
                 return HS_ERR_HIP;
         } else {
             hipError_t e = hsk::launch_zero_i64(counts, p->H + 1, s);
@@ -729,7 +734,7 @@ hs_status hs_detect_batched(const hs_plan* p, const void* const* fops, const int
             a.ta = ta;
             a.out = out;
             a.counts = reinterpret_cast<unsigned long long*>(counts);
-            if (hsk::launch_walk(p->dtype, p->H, a, p->persistent_blocks, p->walk_lds, s) != hipSuccess)
+            if (hsk::launch_walk(p->dtype, p->H, p->walk_v, a, p->persistent_blocks, p->walk_lds, s) != hipSuccess)
                 return HS_ERR_HIP;
             return from_hip(hsk::launch_plane_counts(out, out_offsets, caps, 0,
                                                      reinterpret_cast<unsigned long long*>(counts), p->n_fops,

@@ -307,12 +307,14 @@ hipError_t launch_plane_counts(const hs_cand* out, const int64_t* out_offsets, c
                                hipStream_t s);
 
 // Strip-walk detection (hs_walk_*.hip): whether a plane's thresholds fit
-// the kernel's LDS table, LDS bytes of one block, and the launch.
+// the kernel's LDS table (and the plane has rows enough for its pipeline),
+// which bins-per-lane values V it is built for (strips of 64 V bins), the
+// LDS bytes of a block, and the launcher (grid <= 0: resident grid).
 bool walk_supported(int T, int H);
-int walk_lds_bytes(int T, int H, int dtype);
-constexpr int kWalkStripBins = 256;
+bool walk_v_ok(int V);
+int walk_lds_bytes(int T, int H, int dtype, int V);
 constexpr int kWalkDepth = 2;        // rows in flight per wave; every band has at least this many rows
-hipError_t launch_walk(int dtype, int H, const WalkArgs& a, int grid, int lds_bytes, hipStream_t s);
+hipError_t launch_walk(int dtype, int H, int V, const WalkArgs& a, int grid, int lds_bytes, hipStream_t s);
 
 // Transpose of the plane map and the log-sum-exp statistic (hs_grad.hip).
 int64_t backward_partial_floats(int T, int H, int R, int64_t N);
@@ -358,6 +360,7 @@ struct hs_plan {
     // Strip-walk detection: unit schedule and row table, host copy laid out
     // as the device buffer (offsets in bytes), copied once per device.
     bool walk = false;
+    int walk_v = 4;                      // bins per lane (strips of 64 walk_v bins)
     int band_split = 0;
     std::vector<unsigned char> walk_tab;
     size_t off_xseg = 0, off_rowmask = 0, off_seg = 0, off_nchan = 0, off_ent = 0;

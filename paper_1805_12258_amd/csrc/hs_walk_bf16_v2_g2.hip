@@ -1,0 +1,7 @@
+// Strip-walk detection kernels for bf16 FOP storage, 2 bins per lane,
+// H = 9..12.
+#define HS_WALK_T walk::bf16
+#define HS_WALK_NAME bf16
+#define HS_WALK_V 2
+#define HS_WALK_GROUP 2
+#include "hs_walk_inst.h"

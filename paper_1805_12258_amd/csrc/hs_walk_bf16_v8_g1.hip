@@ -1,5 +1,7 @@
-// Strip-walk detection kernels for bf16 FOP storage, H = 5..8.
+// Strip-walk detection kernels for bf16 FOP storage, 8 bins per lane,
+// H = 5..8.
 #define HS_WALK_T walk::bf16
 #define HS_WALK_NAME bf16
+#define HS_WALK_V 8
 #define HS_WALK_GROUP 1
 #include "hs_walk_inst.h"

@@ -1,0 +1,7 @@
+// Strip-walk detection kernels for f32 FOP storage, 2 bins per lane,
+// H = 1..4.
+#define HS_WALK_T float
+#define HS_WALK_NAME f32
+#define HS_WALK_V 2
+#define HS_WALK_GROUP 0
+#include "hs_walk_inst.h"

@@ -2,21 +2,21 @@
 // arXiv:1805.12258, Sec. III) thresholded into packed candidates, with no
 // plane written to memory.
 //
-// Work decomposition.  A unit is a strip of kWBins = 256 consecutive bins of
-// one row band of the plane: the rows with negative template index, or the
+// Work decomposition.  A unit is a strip of B = 64 V consecutive bins of
+// one row band of the plane (V = 2, 4 or 8 bins per lane, a template
+// parameter chosen per plan): the rows with negative template index, or the
 // rows with non-negative index.  Under the floor of Eq. 1 the two bands read
 // disjoint source rows (floor(i/m) keeps the sign of i), so each band only
 // stages source rows of its own half (the independent half FOPs of Sec. VI-A).
 // One wave owns one unit at a time and walks its rows in increasing order;
-// each lane owns kWV = 4 consecutive bins.  Waves are independent: there is no
+// each lane owns V consecutive bins.  Waves are independent: there is no
 // block barrier inside the walk.
 //
 // Loads.  Every global read is an LDS-DMA (global_load_lds_dwordx4) into
 // rings private to the wave: the m = 1 row of each walked row (a ring of
 // kWDmax rows), and for each stretch factor m >= 2 the shrunken source range
-// [floor(j0/m), floor((j0+255)/m)] of source row floor(i/m) (a ring of
-// ring_slots(m) entries), loaded only when floor(i/m) changes, i.e. every m
-// rows.  The loads of row p + D are issued while row p is summed; the wave
+// [floor(j0/m), floor((j0+B-1)/m)] of source row floor(i/m), loaded only
+// when floor(i/m) changes, i.e. every m rows.  The loads of row p + D are issued while row p is summed; the wave
 // then waits with an exact vmcnt for the loads of the next row (vector memory
 // loads complete in issue order), so D rows stay in flight.  Source values
 // are read from the ring and selected per bin only when a source row
@@ -46,10 +46,7 @@
 namespace hsk {
 namespace walk {
 
-constexpr int kWV = 4;                  // bins per lane
-constexpr int kWBins = 64 * kWV;         // bins per strip (one wave)
 constexpr int kWDmax = 2;               // rows whose loads are in flight (a power of two)
-constexpr int kWCandCap = 320;          // per-wave candidate buffer entries (>= kWBins)
 constexpr int kWWaves = 4;              // waves per block
 constexpr int kWThreads = 64 * kWWaves;
 constexpr int kWThrBytes = 16384;       // largest threshold table (LDS, per block)
@@ -69,12 +66,18 @@ template <> struct St<bf16> {
     static constexpr int EB = 2;
 };
 
+// Bins of a strip for V bins per lane.
+__host__ __device__ constexpr int strip_bins(int V) { return 64 * V; }
+// Per-wave candidate buffer: room for the V * 64 hits one call can add.
+__host__ __device__ constexpr int cand_cap(int V) { return 64 * V > 320 ? 64 * V : 320; }
+
 // Elements of one source slot of stretch factor m: the range
-// [floor(j0/m), floor((j0+255)/m)] (at most floor(255/m) + 2 elements) from a
-// start rounded down to a 16-byte piece (3 more fp32 words or 7 more halves).
-__host__ __device__ constexpr int slot_elems(int m, int EB)
+// [floor(j0/m), floor((j0+B-1)/m)] (at most floor((B-1)/m) + 2 elements)
+// from a start rounded down to a 16-byte piece (3 more fp32 words or 7 more
+// halves).
+__host__ __device__ constexpr int slot_elems(int m, int EB, int V)
 {
-    return EB == 4 ? ((255 / m + 5 + 3) & ~3) : ((255 / m + 9 + 7) & ~7);
+    return EB == 4 ? (((strip_bins(V) - 1) / m + 5 + 3) & ~3) : (((strip_bins(V) - 1) / m + 9 + 7) & ~7);
 }
 // LDS of one wave: a ring of kWDmax rows of m = 1 values (row p in slot
 // p mod kWDmax), then a byte ring of source slots: each source row that a
@@ -84,28 +87,38 @@ __host__ __device__ constexpr int slot_elems(int m, int EB)
 // both sides compute the same slot addresses.  The ring holds the sources of
 // the kWDmax rows in flight: per m at most ceil(D/m) + 1 of them (one more
 // when a unit starts inside the window), plus the bytes lost to one wrap.
+// Then the candidate buffer.  Loads are 16-byte pieces, one per lane and
+// DMA instruction: a region of more than 64 pieces takes several.
 static_assert((kWDmax & (kWDmax - 1)) == 0, "row slots are indexed by the low bits of the row count");
-__host__ __device__ constexpr int x1_bytes(int EB) { return kWBins * EB; }
-__host__ __device__ constexpr int slot_bytes(int m, int EB) { return slot_elems(m, EB) * EB; }
-__host__ __device__ constexpr int slot_pieces(int m, int EB) { return slot_bytes(m, EB) / 16; }
-__host__ __device__ constexpr int src_ring_bytes(int H, int EB)
+__host__ __device__ constexpr int x1_bytes(int EB, int V) { return strip_bins(V) * EB; }
+__host__ __device__ constexpr int x1_pieces(int EB, int V) { return x1_bytes(EB, V) / 16; }
+__host__ __device__ constexpr int slot_bytes(int m, int EB, int V) { return slot_elems(m, EB, V) * EB; }
+__host__ __device__ constexpr int slot_pieces(int m, int EB, int V) { return slot_bytes(m, EB, V) / 16; }
+__host__ __device__ constexpr int dmas(int pieces) { return (pieces + 63) / 64; }
+__host__ __device__ constexpr int src_ring_bytes(int H, int EB, int V)
 {
     int b = 0, mx = 0;
     for (int m = 2; m <= H; ++m) {
-        b += ((kWDmax + m - 1) / m + 1) * slot_bytes(m, EB);
-        mx = slot_bytes(m, EB) > mx ? slot_bytes(m, EB) : mx;
+        b += ((kWDmax + m - 1) / m + 1) * slot_bytes(m, EB, V);
+        mx = slot_bytes(m, EB, V) > mx ? slot_bytes(m, EB, V) : mx;
     }
     return b + mx;
 }
-__host__ __device__ constexpr int src_ring_offset(int EB) { return kWDmax * x1_bytes(EB); }
-__host__ __device__ constexpr int cand_offset(int H, int EB)
+__host__ __device__ constexpr int src_ring_offset(int EB, int V) { return kWDmax * x1_bytes(EB, V); }
+__host__ __device__ constexpr int cand_offset(int H, int EB, int V)
 {
-    return (src_ring_offset(EB) + src_ring_bytes(H, EB) + 15) & ~15;
+    return (src_ring_offset(EB, V) + src_ring_bytes(H, EB, V) + 15) & ~15;
 }
-__host__ __device__ constexpr int wave_bytes(int H, int EB) { return cand_offset(H, EB) + kWCandCap * 8; }
+__host__ __device__ constexpr int wave_bytes(int H, int EB, int V) { return cand_offset(H, EB, V) + cand_cap(V) * 8; }
 // after the waves: the block's flush bookkeeping (2 kWWaves + 2 words), then the thresholds
 constexpr int kWBookBytes = ((2 * kWWaves + 2) * 4 + 15) & ~15;
 __host__ __device__ constexpr int thr_stride(int H) { return (H + 3) & ~3; }
+
+// Source values a lane keeps per stretch factor m: the lane's V bins start
+// at a multiple of V, so when V divides m they share one source element,
+// and when m divides V each group of m bins shares one (V/m elements);
+// otherwise one value per bin.
+__host__ __device__ constexpr int src_vals(int m, int V) { return m % V == 0 ? 1 : (V % m == 0 ? V / m : V); }
 
 typedef __attribute__((address_space(3))) void* lds_ptr_t;
 typedef const __attribute__((address_space(4))) uint32_t* cu32_t;
@@ -211,10 +224,11 @@ struct Iter {
     int s, s_end;   // current segment, end of the XCD's segments
 };
 
-template <typename TIn, int H>
+template <typename TIn, int H, int V>
 struct Walker {
     static constexpr int EB = St<TIn>::EB;
     static constexpr int EPP = 16 / EB;     // elements per 16-byte piece
+    static constexpr int B = strip_bins(V);
 
     const WalkArgs& a;
     int lane;
@@ -242,7 +256,7 @@ struct Walker {
             const uint32_t e = sload_u32(a.ent, (int64_t)eoff + (it.i - pbeg));
             it.i = uni(it.i + step);
             const int band = (int)(e >> 24);
-            u.j0 = uni((int)(e & 0xffffffu) * kWBins);
+            u.j0 = uni((int)(e & 0xffffffu) * B);
             u.r0 = band == 0 ? 0 : a.band_split;
             u.r1 = (band == 0 && a.band_split > 0) ? a.band_split : a.T;
             u.f = f;
@@ -297,23 +311,24 @@ struct Walker {
         }
     }
 
-    // The lane's four m = 1 values of the row in the row slot at `slot`.
-    __device__ __forceinline__ void x1_vals(const unsigned char* slot, float (&x)[kWV]) const
+    // The lane's V m = 1 values of the row in the row slot at `slot`.
+    __device__ __forceinline__ void x1_vals(const unsigned char* slot, float (&x)[V]) const
     {
         if constexpr (EB == 4) {
-            const float* p = reinterpret_cast<const float*>(slot) + kWV * lane;
+            const float* p = reinterpret_cast<const float*>(slot) + V * lane;
 #pragma unroll
-            for (int v = 0; v < kWV; ++v) x[v] = p[v];
+            for (int v = 0; v < V; ++v) x[v] = p[v];
         } else {
-            const uint64_t w = reinterpret_cast<const uint64_t*>(slot)[lane];
+            const uint16_t* p = reinterpret_cast<const uint16_t*>(slot) + V * lane;
+            uint16_t hb[V];
+            __builtin_memcpy(hb, p, sizeof(hb));     // one LDS read of 2V bytes
 #pragma unroll
-            for (int v = 0; v < kWV; ++v) {
-                const uint16_t b = (uint16_t)(w >> (16 * v));
+            for (int v = 0; v < V; ++v) {
                 if constexpr (std::is_same<TIn, bf16>::value) {
-                    x[v] = __uint_as_float((uint32_t)b << 16);
+                    x[v] = __uint_as_float((uint32_t)hb[v] << 16);
                 } else {
                     _Float16 h;
-                    __builtin_memcpy(&h, &b, 2);
+                    __builtin_memcpy(&h, &hb[v], 2);
                     x[v] = (float)h;
                 }
             }
@@ -323,38 +338,43 @@ struct Walker {
 
 }  // namespace walk
 
-// Occupancy asked of the compiler: with 16-bit storage a block's LDS leaves
-// room for six waves per SIMD up to eight planes, which holds without scratch.
-template <typename TIn, int H> constexpr int walk_min_waves() { return (sizeof(TIn) == 2 && H <= 8) ? 6 : 1; }
+// Occupancy asked of the compiler: with 16-bit storage and four bins per
+// lane a block's LDS leaves room for six waves per SIMD up to eight planes,
+// which holds without scratch.
+template <typename TIn, int H, int V>
+constexpr int walk_min_waves() { return (sizeof(TIn) == 2 && H <= 8 && V == 4) ? 6 : 1; }
 
 // The strip-walk detection kernel (see the top of this file).
-template <typename TIn, int H>
-__global__ __launch_bounds__(walk::kWThreads, (walk_min_waves<TIn, H>())) void k_walk(WalkArgs a)
+template <typename TIn, int H, int V>
+__global__ __launch_bounds__(walk::kWThreads, (walk_min_waves<TIn, H, V>())) void k_walk(WalkArgs a)
 {
     using namespace walk;
-    using Wk = Walker<TIn, H>;
+    using Wk = Walker<TIn, H, V>;
     constexpr int EB = Wk::EB;
     constexpr int EPP = Wk::EPP;
+    constexpr int B = Wk::B;
     constexpr int HS = thr_stride(H);
     constexpr int D = kWDmax;
-    constexpr int SRB = src_ring_bytes(H, EB);
+    constexpr int SRB = src_ring_bytes(H, EB, V);
+    constexpr int WB = wave_bytes(H, EB, V);
+    constexpr int CAP = cand_cap(V);
     extern __shared__ __align__(16) unsigned char smem[];
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
 
     // thresholds of every row in storage units (exact: the scale is a power
     // of two), and the waves' per-plane counters
-    int* const book = reinterpret_cast<int*>(smem + kWWaves * wave_bytes(H, EB));
-    float* const thr = reinterpret_cast<float*>(smem + kWWaves * wave_bytes(H, EB) + kWBookBytes);
+    int* const book = reinterpret_cast<int*>(smem + kWWaves * WB);
+    float* const thr = reinterpret_cast<float*>(smem + kWWaves * WB + kWBookBytes);
     for (int e = threadIdx.x; e < a.T * HS; e += kWThreads) {
         const int r = e / HS, k = e - r * HS;
         thr[e] = k < H ? a.ta[(int64_t)k * a.T + r] * a.scale : 0.0f;
     }
-    unsigned char* const wl = smem + wave * wave_bytes(H, EB);
+    unsigned char* const wl = smem + wave * WB;
     __syncthreads();
 
     const Wk w(a);
-    uint64_t* const cbuf = reinterpret_cast<uint64_t*>(wl + cand_offset(H, EB));
+    uint64_t* const cbuf = reinterpret_cast<uint64_t*>(wl + cand_offset(H, EB, V));
 
     // this wave's place in its XCD's unit sequence (blocks are dealt to the
     // eight XCDs in turn); the issue side runs D rows ahead of the consume
@@ -399,7 +419,7 @@ __global__ __launch_bounds__(walk::kWThreads, (walk_min_waves<TIn, H>())) void k
     int iseq = 0;                         // stream index of the next row to issue
     int ihead = 0;                        // byte offset of the source ring's head
     unsigned char* const x1ring = wl;
-    unsigned char* const sring = wl + src_ring_offset(EB);
+    unsigned char* const sring = wl + src_ring_offset(EB, V);
     // byte offsets in a row (wave-uniform, added to the row offset): the
     // strip, and each factor's source range; a lane loads the 16-byte piece
     // lane16 bytes further on
@@ -417,8 +437,9 @@ __global__ __launch_bounds__(walk::kWThreads, (walk_min_waves<TIn, H>())) void k
     issue_unit_start();
 
     // loads of the next row of the stream: the new source ranges (each into
-    // the next slot of the source ring, by as many lane pieces as it holds),
-    // then the row's m = 1 values
+    // the next slot of the source ring, by as many lane pieces as it holds,
+    // 64 pieces per DMA instruction), then the row's m = 1 values; returns
+    // the number of DMA instructions issued
     auto issue_next = [&]() -> int {
         if (!ivalid) return 0;
         if (ir == iu.r1) {
@@ -429,22 +450,32 @@ __global__ __launch_bounds__(walk::kWThreads, (walk_min_waves<TIn, H>())) void k
             ir = iu.r0;
             issue_unit_start();
         }
-        int c = 1;
+        constexpr int XP = x1_pieces(EB, V);
+        int c = dmas(XP);
         if constexpr (H >= 2) {
             const uint32_t fl = ir == iu.r0 ? 0xffffffffu : sload_u32(a.rowmask, ir);
             static_for<2, H>([&](auto mc) {
                 constexpr int m = decltype(mc)::value;
+                constexpr int SP = slot_pieces(m, EB, V);
                 if (fl & (1u << m)) {
-                    const int at = ihead + slot_bytes(m, EB) > SRB ? 0 : ihead;
-                    ihead = at + slot_bytes(m, EB);
+                    const int at = ihead + slot_bytes(m, EB, V) > SRB ? 0 : ihead;
+                    ihead = at + slot_bytes(m, EB, V);
                     const int srow = floordiv_c<m>(ir - a.c) + a.c;
-                    if (lane < slot_pieces(m, EB)) w.dma(isrc, sring + at, lane16, (uint32_t)srow * isrc.ldb + sofs[m]);
-                    ++c;
+                    static_for<0, dmas(SP) - 1>([&](auto gc) {
+                        constexpr int g = decltype(gc)::value;
+                        if (lane + 64 * g < SP)
+                            w.dma(isrc, sring + at + 1024 * g, lane16 + 1024 * g, (uint32_t)srow * isrc.ldb + sofs[m]);
+                    });
+                    c += dmas(SP);
                 }
             });
         }
-        if (EB == 4 || lane < kWBins / EPP)
-            w.dma(isrc, x1ring + (iseq & (D - 1)) * x1_bytes(EB), lane16, (uint32_t)ir * isrc.ldb + sofs1);
+        static_for<0, dmas(XP) - 1>([&](auto gc) {
+            constexpr int g = decltype(gc)::value;
+            if (XP % 64 == 0 || lane + 64 * g < XP)
+                w.dma(isrc, x1ring + (iseq & (D - 1)) * x1_bytes(EB, V) + 1024 * g, lane16 + 1024 * g,
+                      (uint32_t)ir * isrc.ldb + sofs1);
+        });
         ++ir;
         ++iseq;
         return c;
@@ -470,19 +501,19 @@ __global__ __launch_bounds__(walk::kWThreads, (walk_min_waves<TIn, H>())) void k
     int jb = 0;
     bool full = true;
     int lofsb[H + 1], rmod[H + 1];
-    float sv[H + 1][kWV];
+    float sv[H + 1][V];
 #pragma unroll
     for (int m = 0; m <= H; ++m) {
         lofsb[m] = rmod[m] = 0;
 #pragma unroll
-        for (int v = 0; v < kWV; ++v) sv[m][v] = 0.0f;
+        for (int v = 0; v < V; ++v) sv[m][v] = 0.0f;
     }
     auto unit_setup = [&]() {
-        jb = cu.j0 + kWV * lane;
-        full = cu.j0 + kWBins <= cu.N;
+        jb = cu.j0 + V * lane;
+        full = cu.j0 + B <= cu.N;
         static_for<2, H>([&](auto mc) {
             constexpr int m = decltype(mc)::value;
-            const uint32_t t = (uint32_t)cu.j0 + (uint32_t)(kWV * lane);
+            const uint32_t t = (uint32_t)cu.j0 + (uint32_t)(V * lane);
             const uint32_t q = t / (uint32_t)m;
             const uint32_t base = ((uint32_t)cu.j0 / (uint32_t)m) & ~(uint32_t)(EPP - 1);
             rmod[m] = (int)(t - q * (uint32_t)m);
@@ -532,17 +563,17 @@ __global__ __launch_bounds__(walk::kWThreads, (walk_min_waves<TIn, H>())) void k
     };
 
     // hits of plane k among the lane's values (the rare path, whole wave);
-    // `lanes` lanes have one, so the call adds at most kWV * lanes entries.
+    // `lanes` lanes have one, so the call adds at most V * lanes entries.
     // The buffer is written out only when that many might not fit, so that a
     // flush carries a nearly full buffer (each flush costs one atomic on the
     // list's shared counter).
-    static_assert(kWCandCap >= kWBins, "candidate buffer");
-    auto emit = [&](auto kc, const float (&acc)[kWV], float tk, int r, int lanes) __attribute__((always_inline)) {
+    static_assert(CAP >= B, "candidate buffer");
+    auto emit = [&](auto kc, const float (&acc)[V], float tk, int r, int lanes) __attribute__((always_inline)) {
         constexpr int k = decltype(kc)::value;
         const uint32_t hi = ((uint32_t)r << a.s_row) | ((uint32_t)(k - 1) << a.s_bin);
-        if (ncand + kWV * lanes > kWCandCap) flush();
+        if (ncand + V * lanes > CAP) flush();
 #pragma unroll
-        for (int v = 0; v < kWV; ++v) {
+        for (int v = 0; v < V; ++v) {
             const bool hit = acc[v] > tk;
             const uint64_t mk = __builtin_amdgcn_ballot_w64(hit);
             if (mk) {
@@ -602,40 +633,51 @@ __global__ __launch_bounds__(walk::kWThreads, (walk_min_waves<TIn, H>())) void k
             static_for<2, H>([&](auto mc) {
                 constexpr int m = decltype(mc)::value;
                 if (fl & (1u << m)) {
-                    const int at = ctail + slot_bytes(m, EB) > SRB ? 0 : ctail;
-                    ctail = at + slot_bytes(m, EB);
+                    const int at = ctail + slot_bytes(m, EB, V) > SRB ? 0 : ctail;
+                    ctail = at + slot_bytes(m, EB, V);
                     const unsigned char* p = sring + at + lofsb[m];
-                    if constexpr (m == 2) {
-                        sv[m][0] = w.elem(p, 0);
-                        sv[m][1] = w.elem(p, 1);
-                    } else if constexpr (kWBins % m == 0) {
-                        sv[m][0] = w.elem(p, 0);      // the lane's bins share one source element
-                    } else {
-                        const float w0 = w.elem(p, 0), w1 = w.elem(p, 1);
-                        sv[m][0] = w0;
+                    if constexpr (src_vals(m, V) < V) {
+                        // one element per group of m bins (or one for all)
 #pragma unroll
-                        for (int v = 1; v < kWV; ++v) sv[m][v] = rmod[m] + v >= m ? w1 : w0;
+                        for (int g = 0; g < src_vals(m, V); ++g) sv[m][g] = w.elem(p, g);
+                    } else {
+                        // bin v reads element (rmod + v) / m of the lane's
+                        // range, which spans (V - 1) / m + 2 elements at most
+                        constexpr int NE = (V - 1) / m + 2;
+                        float e[NE];
+#pragma unroll
+                        for (int q = 0; q < NE; ++q) e[q] = w.elem(p, q);
+#pragma unroll
+                        for (int v = 0; v < V; ++v) {
+                            float x = e[0];
+#pragma unroll
+                            for (int q = 1; q < NE; ++q)
+                                if (rmod[m] + v >= q * m) x = e[q];
+                            sv[m][v] = x;
+                        }
                     }
                 }
             });
         }
 
-        float x[kWV];
-        w.x1_vals(x1ring + (cseq & (D - 1)) * x1_bytes(EB), x);
-        float acc[kWV];
+        float x[V];
+        w.x1_vals(x1ring + (cseq & (D - 1)) * x1_bytes(EB, V), x);
+        float acc[V];
         if (full) {
 #pragma unroll
-            for (int v = 0; v < kWV; ++v) acc[v] = x[v];
+            for (int v = 0; v < V; ++v) acc[v] = x[v];
         } else {
             // bins past the end start at -inf: no sum of them passes a threshold
 #pragma unroll
-            for (int v = 0; v < kWV; ++v) acc[v] = jb + v < cu.N ? x[v] : -__builtin_inff();
+            for (int v = 0; v < V; ++v) acc[v] = jb + v < cu.N ? x[v] : -__builtin_inff();
         }
 
         auto detect = [&](auto kc) __attribute__((always_inline)) {
             constexpr int k = decltype(kc)::value;
             const float tk = t[k - 1];
-            const float mx = fmaxf(fmaxf(acc[0], acc[1]), fmaxf(acc[2], acc[3]));
+            float mx = acc[0];
+#pragma unroll
+            for (int v = 1; v < V; ++v) mx = fmaxf(mx, acc[v]);
             const uint64_t any = __builtin_amdgcn_ballot_w64(mx > tk);
             if (__builtin_expect(any != 0, 0)) emit(kc, acc, tk, r, __builtin_popcountll(any));
         };
@@ -643,10 +685,10 @@ __global__ __launch_bounds__(walk::kWThreads, (walk_min_waves<TIn, H>())) void k
         static_for<2, H>([&](auto mc) {
             constexpr int m = decltype(mc)::value;
 #pragma unroll
-            for (int v = 0; v < kWV; ++v) {
+            for (int v = 0; v < V; ++v) {
                 float s;
-                if constexpr (m == 2) s = sv[m][v >> 1];
-                else if constexpr (kWBins % m == 0) s = sv[m][0];
+                if constexpr (src_vals(m, V) == 1) s = sv[m][0];
+                else if constexpr (src_vals(m, V) < V) s = sv[m][v / m];
                 else s = sv[m][v];
                 acc[v] = acc[v] + s;
             }
@@ -675,10 +717,10 @@ __global__ __launch_bounds__(walk::kWThreads, (walk_min_waves<TIn, H>())) void k
     }
 }
 
-template <typename TIn, int H>
+template <typename TIn, int H, int V>
 hipError_t launch_walk_t(const WalkArgs& a, int grid, int lds_bytes, hipStream_t s)
 {
-    auto k = k_walk<TIn, H>;
+    auto k = k_walk<TIn, H, V>;
     (void)hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, lds_bytes);
     if (grid <= 0) {
         int dev = 0, cus = 0, per_cu = 0;

@@ -212,3 +212,21 @@ def test_batched_real_lengths_h16():
         assert np.array_equal(gc, wc), (f, gc, wc)
         assert gc[-1] > 10000
         assert np.array_equal(triples(gi, gp, s_row, s_bin), want), f
+
+
+@pytest.mark.parametrize("V", [2, 8])
+def test_batched_walk_bins_per_lane(V):
+    """The batched strip walk with 2 and 8 bins per lane equals the oracle."""
+    H, T = 8, 21
+    devs, stores = make_batch(LENS, T, H, 9300 + V)
+    ta = synth.thresholds(H, T)
+    plan = hs.Plan(T, 0, H, n_chans=LENS, schedule=4, bins_per_lane=V)
+    assert plan.info["bins_per_lane"] == V
+    caps = [H * T * n + 8 for n in LENS]
+    (_, _, _, out, _, _, counts), offs = batched_call(plan, devs, ta, caps)
+    res = unpack_batched(out, counts, offs, caps)
+    for f in range(len(LENS)):
+        gi, gp, gc = res[f]
+        want, wc = oracle_triples(stores[f], H, ta)
+        assert np.array_equal(gc, wc), f
+        assert np.array_equal(triples(gi, gp, plan.info["s_row"], plan.info["s_bin"]), want), f

@@ -414,3 +414,22 @@ def test_select_refines_crowded_digits():
     for policy in ("last_alg2", "last_alg1", "top"):
         for n_cand in (1, 300, 1024):
             _check_select(plan, out, n, wi, wp, N, H, n_cand, policy)
+
+
+@pytest.mark.parametrize("V", [2, 4, 8])
+@pytest.mark.parametrize("name,dtype,H", [("f32", torch.float32, 8), ("f32", torch.float32, 16),
+                                          ("f16", torch.float16, 5), ("bf16", torch.bfloat16, 13)])
+def test_walk_bins_per_lane(V, name, dtype, H):
+    """The strip walk with 2, 4 and 8 bins per lane (strips of 128, 256 and
+    512 bins), over ragged strips and both row bands: candidates bitwise
+    equal to the oracle's, for fp32 and 16-bit storage."""
+    T, N = 85, 512 * 9 + 136
+    print("case", V, name, H, flush=True)
+    x = exp_plane(T, N, 1000 + V + H)
+    ta = random_thresholds(H, T, 2000 + V)
+    scale = 1.0 if name == "f32" else 0.125
+    dev, store = padded_device(x, dtype=dtype, scale=scale)
+    plan = hs.Plan(T, N, H, dtype=name, input_scale=scale, schedule=4, bins_per_lane=V)
+    assert plan.info["detector"] == 1 and plan.info["bins_per_lane"] == V
+    got = gpu_detect(plan, dev, ta, capacity=H * T * N)
+    assert_same_candidates(got, oracle_detect_sorted(store, H, ta, scale=scale))

@@ -179,6 +179,13 @@ def test_detector_choice():
     assert [det(85, 8, "f32", s) for s in range(5)] == [0, 1, 0, 0, 1]
     assert [det(85, 16, "f16", s) for s in range(5)] == [1, 1, 0, 0, 1]
     assert det(1, 16) == 0 and det(1, 8, "f16", 4) == 0          # T < 2
+    for V in (2, 4, 8):
+        p = hs.Plan(85, N, 8, schedule=4, bins_per_lane=V)
+        assert p.info["bins_per_lane"] == V and p.info["detector"] == 1
+    assert hs.Plan(85, N, 8, bins_per_lane=8).info["bins_per_lane"] == 0   # tile kernel: no walk
+    for bad in (1, 3, 16, -2):
+        with pytest.raises(hs.HsError):
+            hs.Plan(85, N, 8, bins_per_lane=bad)
     assert det(257, 16, "f32", 4) == 0                            # 257 x 16 x 4 B > 16 KB
     assert det(256, 16, "f32", 4) == 1
     with pytest.raises(hs.HsError):
@@ -190,17 +197,24 @@ def test_autotune_search_and_cache(tmp_path):
     skips invalid ones, and the cache round-trips."""
     from paper_1805_12258_amd import autotune as at
     cfgs = at.candidates(True, cus=256)
-    assert len(cfgs) == len(at.TILE_ROWS) * len(at.GRID_FACTORS) * len(at.SCHEDULES)
-    assert all(c["schedule"] == 0 for c in at.candidates(False, cus=256))
-    assert cfgs[0] == {"tile_rows": 0, "persistent_blocks": 0, "schedule": 0}   # planner defaults first
+    per_grid = 2 * (len(at.BINS_PER_LANE) + len(at.TILE_ROWS))
+    assert len(cfgs) == 1 + len(at.GRID_FACTORS) * per_grid
+    assert cfgs[0] == {"schedule": 0}                                            # planner defaults first
+    assert {c.get("bins_per_lane") for c in cfgs} >= {2, 4, 8}                  # B = 128, 256, 512
+    batched = at.candidates(False, cus=256)
+    assert all(c["schedule"] in (0, 2, 4) for c in batched)                     # XCD orders only
+    assert len(batched) == 1 + len(at.GRID_FACTORS) * (len(at.BINS_PER_LANE) + len(at.TILE_ROWS))
     times = {i: 5.0 - (i % 4) for i in range(len(cfgs))}
     times[3] = None
     best, ms, tried = at.search(cfgs, lambda c: times[cfgs.index(c)], margin=0.0)
     assert ms == min(v for v in times.values() if v is not None)
     assert cfgs.index(best) == min(i for i, v in times.items() if v == ms)
+    sm = at.summary(best, ms, tried)
+    assert sm["default_ms"] == times[0] and sm["config"] == best
+    assert sm["runner_up_ms"] >= ms and sm["margin_vs_runner_up"] >= 0.0
     assert len(tried) == len(cfgs)
     # within the margin the incumbent stays
-    near = {i: 5.0 - 0.005 * i for i in range(len(cfgs))}      # at most 1.1 % faster
+    near = {i: 5.0 - 0.05 * i / len(cfgs) for i in range(len(cfgs))}   # under 1 % faster
     best, ms, _ = at.search(cfgs, lambda c: near[cfgs.index(c)], margin=0.02)
     assert best == cfgs[0] and ms == 5.0
     with pytest.raises(RuntimeError):
