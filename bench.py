@@ -1,22 +1,30 @@
 """Benchmark: fused harmonic summing + detection on one MI355X.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-variants]
-                    [--batched-fops N] [--copy-calibration]
+                    [--batched-fops N] [--copy-calibration] [--launch JSON]
+    python bench.py --traffic-summary FETCH_CSV WRITE_CSV --launch JSON --traffic-cmds C1 C2
 
 Workload: one filter-output plane of 85 templates x 2^21 bins of fp32 power
 (Exp(1) noise, 50 injected harmonic signals, seed 2), 8 harmonic planes,
 thresholds T_k = k + 6 sqrt(k), full candidate list.  A step is one
-hs_detect call (counter clear + fused kernel) over the plane, which is
+hs_detect call (counter clear + detection kernel) over the plane, which is
 resident in HBM before the timed region starts.
 
+The launch configuration is the autotuner's choice for the plane (every
+candidate timed on the resident input before the timed region; the planner's
+defaults stay unless another candidate is faster by more than 2 %); the line
+reports it with its margins under `autotuned`.
+
 Prints one JSON line.  `value` is FOP points per second (every point taken
-through all 8 planes and the threshold test).  `roofline` refers to the fused
-kernel: algorithmic bytes (one read of the FOP + 8 bytes per candidate + the
-counters) over its average launch time, measured with HIP events on the
-launch stream.  `traffic` comes from rocprofv3 FETCH_SIZE / WRITE_SIZE
-counters recorded in profiles/ for the current kernel sources (null when the
-sources changed since).  `cpu_baseline` times the CPU oracle on a bounded
-sample of the same plane.
+through all 8 planes and the threshold test).  `roofline` refers to the
+detection kernel the chosen plan launches: algorithmic bytes (one read of
+the FOP + 8 bytes per candidate + the counters) over its average launch
+time, measured with HIP events on the launch stream.  `traffic` comes from
+rocprofv3 FETCH_SIZE / WRITE_SIZE counters recorded in profiles/ for that
+kernel and its current sources (null otherwise).  `read_ceiling` times one
+streaming read of the plane (hs_stream_read), the bound the detection
+kernel is compared against.  `cpu_baseline` times the CPU oracle on a
+bounded sample of the same plane.
 """
 import argparse
 import hashlib
@@ -32,11 +40,9 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-KERNEL_SOURCES = ["paper_1805_12258_amd/csrc/hs_fused_impl.h",
-                  "paper_1805_12258_amd/csrc/hs_fused_inst.h",
-                  "paper_1805_12258_amd/csrc/hs_fused_f32_g1.hip",
-                  "paper_1805_12258_amd/csrc/hs_internal.h"]
+CSRC = "paper_1805_12258_amd/csrc/"
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "ska_detect_f32_traffic.json")
+CTYPE = {"f32": "float", "f16": "_Float16", "bf16": "bf16"}
 
 
 def log(msg):
@@ -44,22 +50,61 @@ def log(msg):
     print("bench: " + msg, file=sys.stderr, flush=True)
 
 
-def kernel_source_hash():
+def detection_kernel(plan, dtype="f32"):
+    """Name of the detection kernel the plan launches and the sources it is
+    built from (the tile kernel, the strip walk at V bins per lane or the
+    fractional-mapping kernel)."""
+    info, H = plan.info, plan.n_hp
+    g = (H - 1) // 4
+    if info["detector"] == 1:
+        v = info["bins_per_lane"]
+        return ("k_walk<%s,%d,%d>" % (CTYPE[dtype], H, v),
+                [CSRC + "hs_walk_impl.h", CSRC + "hs_walk_inst.h",
+                 CSRC + "hs_walk_%s_v%d_g%d.hip" % (dtype, v, g), CSRC + "hs_internal.h"])
+    if info["detector"] == 2:
+        return ("k_frac<%s,detect>" % CTYPE[dtype], [CSRC + "hs_frac.hip", CSRC + "hs_internal.h"])
+    return ("k_fused<%s,%d,detect>" % (CTYPE[dtype], H),
+            [CSRC + "hs_fused_impl.h", CSRC + "hs_fused_inst.h",
+             CSRC + "hs_fused_%s_g%d.hip" % (dtype, g), CSRC + "hs_internal.h"])
+
+
+def kernel_source_hash(sources):
     h = hashlib.sha256()
-    for f in KERNEL_SOURCES:
+    for f in sources:
         h.update(open(os.path.join(ROOT, f), "rb").read())
     return h.hexdigest()[:16]
 
 
-def stored_traffic():
-    """Per-launch HBM bytes of the fused kernel from the committed counter
-    summary, or None when it was taken on different kernel sources."""
+def stored_traffic(kernel, sources):
+    """Per-launch HBM bytes of the detection kernel from the committed
+    counter summary, or None when it was taken on another kernel or on
+    different kernel sources."""
     if not os.path.exists(TRAFFIC_FILE):
         return None
     d = json.load(open(TRAFFIC_FILE))
-    if d.get("source_hash") != kernel_source_hash():
+    if d.get("kernel") != kernel or d.get("source_hash") != kernel_source_hash(sources):
         return None
     return d
+
+
+def tuned_plan(T, N, H, store, ta, dtype="f32", input_scale=1.0, reps=20, launch=None):
+    """The autotuner's choice for this plane (every candidate timed on the
+    resident input), and a summary: the configuration, its time, the
+    planner's default time and the margin over the runner-up.  A given
+    `launch` configuration is taken as it is (no tuning)."""
+    import paper_1805_12258_amd as hs
+    from paper_1805_12258_amd import autotune
+    if launch is not None:
+        plan = hs.Plan(T, N, H, dtype=dtype, input_scale=input_scale, **launch)
+        return plan, {"config": launch, "tuned": False, "kernel": detection_kernel(plan, dtype)[0]}
+    t0 = time.perf_counter()
+    best, ms, tried = autotune.tune(T, N, H, dtype=dtype, input_scale=input_scale, fops=store, ta=ta,
+                                    reps=reps, cache=None)
+    sm = autotune.summary(best, ms, tried)
+    sm["tuning_s"] = time.perf_counter() - t0
+    plan = hs.Plan(T, N, H, dtype=dtype, input_scale=input_scale, **best)
+    sm["kernel"] = detection_kernel(plan, dtype)[0]
+    return plan, sm
 
 
 def time_detect(plan, fop, ta, capacity, steps, warmup):
@@ -163,7 +208,7 @@ def precision_recall(words, ref_words):
     return common / len(words), common / len(ref_words)
 
 
-def batched_leg(n_fops, steps, warmup, dev):
+def batched_leg(n_fops, steps, warmup, dev, launch=None):
     """The batched workload: n_fops FOPs of 85 templates and 2^19, 2^20 or
     2^21 bins (seeded), 16 planes, in one persistent launch replayed from a
     captured HIP graph, against one hs_detect launch per FOP."""
@@ -191,7 +236,12 @@ def batched_leg(n_fops, steps, warmup, dev):
     from paper_1805_12258_amd import autotune
     t_tune = time.perf_counter()
     sub = min(64, n_fops)
-    tuned, tuned_ms, _ = autotune.tune(T, 0, H, n_chans=lens[:sub], fops=fops[:sub], ta=ta, reps=3, cache=None)
+    if launch is None:
+        tuned, tuned_ms, tried = autotune.tune(T, 0, H, n_chans=lens[:sub], fops=fops[:sub], ta=ta, reps=3,
+                                               cache=None)
+        summary = autotune.summary(tuned, tuned_ms, tried)
+    else:
+        tuned, summary = launch, {"config": launch, "tuned": False}
     t_tune = time.perf_counter() - t_tune
     plan = hs.Plan(T, 0, H, n_chans=lens, **tuned)
     args = (plan.handle, fop_ptrs, lds, ta, out, offs_d, caps_d, counts)
@@ -267,7 +317,7 @@ def batched_leg(n_fops, steps, warmup, dev):
             "candidates": int(batched_counts[:, -1].sum().item()),
             "lists_equal_per_fop": True,
             "launch": "one persistent kernel replayed from a captured HIP graph",
-            "autotuned": {"config": tuned, "on_fops": sub, "tuning_s": t_tune}}
+            "autotuned": dict(summary, on_fops=sub, tuning_s=t_tune)}
 
 
 def precision_leg(n_fops, dev, threads):
@@ -402,6 +452,95 @@ def diff_leg(n_fops, steps, warmup, dev):
     return out
 
 
+def read_ceiling(fop, reps=20):
+    """The streaming-read ceiling for the plane: hs_stream_read of the whole
+    resident FOP at several grid sizes, median launch time of each (HIP
+    events on the launch stream), the best grid reported."""
+    import paper_1805_12258_amd as hs
+    nbytes = fop.numel() * fop.element_size()
+    sink = torch.empty(8192, dtype=torch.float32, device=fop.device)
+    res = {}
+    for g in (2048, 4096, 8192):
+        for _ in range(3):
+            hs.hs_stream_read(fop, nbytes, sink, g)
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
+        for a, b in ev:
+            a.record()
+            hs.hs_stream_read(fop, nbytes, sink, g)
+            b.record()
+        torch.cuda.synchronize()
+        res[g] = float(np.median([a.elapsed_time(b) for a, b in ev]))
+    g = min(res, key=res.get)
+    us = res[g] * 1e3
+    return {"kernel": "k_stream_read", "bytes": nbytes, "grid": g, "us_median": us,
+            "gbs": nbytes / (us * 1e-6) / 1e9, "frac": nbytes / (us * 1e-6) / 1e9 / HBM_PEAK_GBS,
+            "us_by_grid": {str(k): v * 1e3 for k, v in res.items()}}
+
+
+def traffic_summary(fetch_csv, write_csv, launch, cmds):
+    """Writes the committed traffic figures of the detection kernel from two
+    rocprofv3 counter runs of `bench.py --copy-calibration --launch ...`
+    (FETCH_SIZE, then WRITE_SIZE): per-dispatch medians, each scaled by what
+    the same counter reads for torch's copy of the plane (713031680 bytes
+    each way)."""
+    import csv
+    import statistics
+    import paper_1805_12258_amd as hs
+    import synth
+    cfg = synth.SKA
+    T, N, H = cfg["n_temp"], cfg["n_chan"], cfg["n_hp"]
+    plan = hs.Plan(T, N, H, **launch)
+    kname, ksrc = detection_kernel(plan)
+    base = kname.split("<")[0]
+    targs = kname[kname.index("<") + 1:-1].split(",")
+    if base == "k_fused":
+        targs[-1] = "0"                                    # Mode: detect
+    match = "%s<%s>" % (base, ", ".join(targs))
+    plane = T * N * 4
+
+    def medians(path, counter):
+        k, c = [], []
+        for r in csv.DictReader(open(path)):
+            if r["Counter_Name"] != counter:
+                continue
+            if match in r["Kernel_Name"]:
+                k.append(float(r["Counter_Value"]))
+            elif "copy" in r["Kernel_Name"].lower():
+                c.append(float(r["Counter_Value"]))
+        if not k or not c:
+            raise SystemExit("%s: no %s dispatches of %s or of the copy kernel" % (path, counter, match))
+        return statistics.median(k), statistics.median(c), len(k)
+
+    fk, fc, nf = medians(fetch_csv, "FETCH_SIZE")
+    wk, wc, nw = medians(write_csv, "WRITE_SIZE")
+    fscale, wscale = plane / (fc * 1024), plane / (wc * 1024)
+    d = {"source_hash": kernel_source_hash(ksrc), "kernel": kname, "launch": launch,
+         "workload": "85 x 2^21 fp32, H=8, thresholds k+6*sqrt(k)",
+         "fetch_kib_raw": fk, "write_kib_raw": wk, "dispatches": [nf, nw],
+         "copy_bytes": plane, "copy_fetch_kib": fc, "copy_write_kib": wc,
+         "fetch_scale": fscale, "write_scale": wscale,
+         "fetch_bytes": fk * 1024 * fscale, "write_bytes": wk * 1024 * wscale,
+         "fetch_cmd": cmds[0], "write_cmd": cmds[1]}
+    with open(TRAFFIC_FILE, "w") as f:
+        json.dump(d, f, indent=1)
+        f.write("\n")
+    md = ["# HBM-side traffic of the detection kernel %s (85 x 2^21 fp32, H=8)" % kname, "",
+          "Launch configuration %s.  Commands (repository root, TMPDIR=/tmp), one counter per run:" %
+          json.dumps(launch), "", "    " + cmds[0], "    " + cmds[1], "",
+          "Calibration: torch's copy of the plane (%d B each way) reads FETCH_SIZE %.1f KiB and "
+          "WRITE_SIZE %.1f KiB, so FETCH_SIZE is scaled by %.4f and WRITE_SIZE by %.4f." %
+          (plane, fc, wc, fscale, wscale), "",
+          "| per launch (median of %d / %d dispatches) | raw KiB | scaled bytes | vs one read of the plane |" %
+          (nf, nw), "|---|---|---|---|",
+          "| FETCH_SIZE | %.1f | %.4g | %.3f |" % (fk, d["fetch_bytes"], d["fetch_bytes"] / plane),
+          "| WRITE_SIZE | %.1f | %.4g | %.4f |" % (wk, d["write_bytes"], d["write_bytes"] / plane), "",
+          "Kernel source hash %s: bench.py reports these bytes as roofline.traffic only while the "
+          "plan launches this kernel and its sources hash to this value." % d["source_hash"], ""]
+    with open(TRAFFIC_FILE[:-5] + ".md", "w") as f:
+        f.write("\n".join(md))
+    print(json.dumps(d, indent=1))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -420,7 +559,21 @@ def main():
                     help="FOPs of the precision leg taken through the fp64 oracle (0 skips it)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one plain device copy of the FOP's size (counter scale)")
+    ap.add_argument("--launch", default="{}",
+                    help='launch configurations as JSON, {"f32": {...}, "f16": {...}, "bf16": {...}, '
+                         '"batched": {...}} of Plan keyword arguments; a leg not named takes the '
+                         "autotuner's choice")
+    ap.add_argument("--no-read-ceiling", action="store_true")
+    ap.add_argument("--traffic-summary", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
+                    help="write the traffic figures under profiles/ from two counter runs "
+                         "(with --launch and --traffic-cmds) and exit; runs on the CPU")
+    ap.add_argument("--traffic-cmds", nargs=2, default=["", ""])
     args = ap.parse_args()
+    launch = json.loads(args.launch)
+    if args.traffic_summary:
+        traffic_summary(args.traffic_summary[0], args.traffic_summary[1],
+                        launch.get("f32", {"schedule": 0}), args.traffic_cmds)
+        return
     if args.gpus != 1:
         print("bench.py measures one GPU: the harmonic-summing path here runs on a single "
               "MI355X (--gpus %d is not supported)" % args.gpus, file=sys.stderr)
@@ -436,7 +589,9 @@ def main():
     ta_np = synth.thresholds(H, T)
     ta = torch.from_numpy(ta_np).to(dev)
     capacity = 1 << 22
-    plan = hs.Plan(T, N, H)
+    plan, tuned = tuned_plan(T, N, H, fop, ta, launch=launch.get("f32"))
+    kname, ksrc = detection_kernel(plan)
+    log("autotuned: %s" % tuned)
     torch.cuda.synchronize()
 
     if args.copy_calibration:
@@ -454,7 +609,7 @@ def main():
     n_cand = int(r["counts"][-1])
     alg_bytes = points * 4 + 8 * n_cand + 8 * (H + 1)
     achieved = alg_bytes / (r["launch_ms"] * 1e-3) / 1e9
-    tr = stored_traffic()
+    tr = stored_traffic(kname, ksrc)
     traffic = None
     if tr is not None:
         traffic = tr["fetch_bytes"] + tr["write_bytes"]
@@ -473,14 +628,21 @@ def main():
         "dtype": "f32",
         "data": "synthetic: Exp(1) noise + 50 injected harmonic signals, seed 2",
         "config": {"workload": "ska-plain", "n_temp": T, "n_chan": N, "n_hp": H,
-                   "thresholds": "k+6*sqrt(k)", "candidates": n_cand},
+                   "thresholds": "k+6*sqrt(k)", "candidates": n_cand, "launch": tuned["config"]},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                     "kernel": "k_fused<float,8,detect>", "launch_ms": r["launch_ms"],
+                     "kernel": kname, "launch_ms": r["launch_ms"],
                      "algorithmic_bytes": alg_bytes},
+        "autotuned": tuned,
         "hbm_gbs": achieved,
         "plane_points_per_s": H * points / (r["ms_per_step"] * 1e-3),
     }
+
+    if not args.no_read_ceiling:
+        rc = read_ceiling(fop)
+        rc["detection_vs_ceiling"] = rc["us_median"] / (r["launch_ms"] * 1e3)
+        line["read_ceiling"] = rc
+        log("read ceiling: %.1f us (%.0f GB/s)" % (rc["us_median"], rc["gbs"]))
 
     # materialised planes (hs_sum): 4 B read + 4H B written per point
     hp = torch.empty((H, T, N), dtype=torch.float32, device=dev)
@@ -575,7 +737,7 @@ def main():
         for name, dt in (("f16", torch.float16), ("bf16", torch.bfloat16)):
             scale = synth.PRECISION["input_scale"]
             store = synth.quantize(fop, dt, scale)
-            p2 = hs.Plan(T, N, H, dtype=name, input_scale=scale)
+            p2, t2 = tuned_plan(T, N, H, store, ta, dtype=name, input_scale=scale, launch=launch.get(name))
             r2 = time_detect(p2, store, ta, capacity, max(20, args.steps // 2), 5)
             o2, c2 = p2.detect(store, ta, capacity=capacity)
             prec, rec = precision_recall(candidate_words(o2, c2), ref_words)
@@ -584,6 +746,7 @@ def main():
                          "ms_per_step": r2["ms_per_step"], "launch_ms": r2["launch_ms"],
                          "hbm_gbs": ab / (r2["launch_ms"] * 1e-3) / 1e9,
                          "vs_f32": r["ms_per_step"] / r2["ms_per_step"],
+                         "kernel": t2["kernel"], "autotuned": t2,
                          "candidates": int(r2["counts"][-1]),
                          "precision_vs_f32": prec, "recall_vs_f32": rec,
                          "storage": "%s of power x %g, fp32 sums" % (name, scale)}
@@ -595,7 +758,7 @@ def main():
         del fop, ref_out
         torch.cuda.empty_cache()
         line["batched"] = batched_leg(args.batched_fops, max(3, args.steps // 40),
-                                      2, dev)
+                                      2, dev, launch=launch.get("batched"))
         log("batched: %.3f ms" % line["batched"]["ms_per_step"])
         fop = synth.make_ska(device=dev)
 

@@ -314,6 +314,16 @@ hs_status hs_lse_backward(const hs_plan* plan, const void* fop, int64_t ld, cons
 hs_status hs_lse_forward_noalloc(const hs_plan* plan, const void* fop, int64_t ld, float tau, double* lse,
                                  double* loss, void* stream);
 
+/* Measurement: one streaming read of `bytes` bytes at `src` (device,
+ * 16-byte aligned, bytes a multiple of 16) by `grid` blocks of 256 threads
+ * (1..65536) with 16-byte loads.  Block b writes the fp32 sum
+ * of the words it read to sink[b] (device, `grid` floats), so the sum of
+ * sink is the sum of the buffer's fp32 values (up to rounding order).  Its
+ * time over a resident FOP is the read-bandwidth ceiling the detection
+ * kernels are compared against (they read the FOP once).  HS_ERR_INVALID
+ * for a bad pointer, size, alignment or grid. */
+hs_status hs_stream_read(const void* src, int64_t bytes, float* sink, int32_t grid, void* stream);
+
 /* Host check of counts copied back from hs_detect: HS_ERR_OVERFLOW when
  * counts[n_hp] > capacity, HS_OK otherwise. */
 hs_status hs_check_counts(const int64_t* counts_host, int32_t n_hp, int64_t capacity);

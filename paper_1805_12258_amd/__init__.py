@@ -89,6 +89,7 @@ _SIG = {
     "hs_lse_forward_noalloc": ([_P, _P, _I64, ctypes.c_float, _P, _P, _P], ctypes.c_int),
     "hs_lse_backward": ([_P, _P, _I64, _P, ctypes.c_float, _P, _P, _P, _P],
                         ctypes.c_int),
+    "hs_stream_read": ([_P, _I64, _P, ctypes.c_int32, _P], ctypes.c_int),
     "hs_check_counts": ([ctypes.POINTER(ctypes.c_int64), ctypes.c_int32, _I64], ctypes.c_int),
     "hs_status_string": ([ctypes.c_int], ctypes.c_char_p),
     "hs_version": ([], ctypes.c_char_p),
@@ -250,6 +251,17 @@ def hs_sort_candidates(cand, n, work, stream=None):
     _need_cuda(cand, work)
     _check(_c_hs_sort_candidates(_ptr(cand), int(n), _ptr(work), _stream(stream)),
            "hs_sort_candidates")
+
+
+def hs_stream_read(src, nbytes, sink, grid, stream=None):
+    """One streaming read of `nbytes` bytes of `src` by `grid` blocks; block b
+    writes the sum of its fp32 words to sink[b]."""
+    _need_cuda(src, sink)
+    if sink.dtype != torch.float32 or sink.numel() < int(grid):
+        raise ValueError("sink must hold at least grid fp32 values")
+    if src.numel() * src.element_size() < int(nbytes):
+        raise ValueError("src holds fewer than nbytes bytes")
+    _check(_c_hs_stream_read(_ptr(src), int(nbytes), _ptr(sink), int(grid), _stream(stream)), "hs_stream_read")
 
 
 def hs_backward_workspace_bytes(handle):

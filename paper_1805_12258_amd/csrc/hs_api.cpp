@@ -954,6 +954,18 @@ const char* hs_status_string(hs_status s)
     return "unknown status";
 }
 
+hs_status hs_stream_read(const void* src, int64_t bytes, float* sink, int32_t grid, void* stream)
+{
+    if (!src || !sink || bytes <= 0 || bytes % 16 != 0 || (reinterpret_cast<uintptr_t>(src) & 15) != 0 ||
+        grid < 1 || grid > 65536)
+        return HS_ERR_INVALID;
+    try {
+        return from_hip(hsk::launch_stream_read(src, bytes, sink, grid, (hipStream_t)stream));
+    } catch (...) {
+        return HS_ERR_HIP;
+    }
+}
+
 const char* hs_version(void) { return "hs-mi355x 0.1.0 (gfx950)"; }
 
 }  // extern "C"

@@ -178,6 +178,41 @@ hipError_t launch_batched(int dtype, int H, const BatchArgs& b, int grid, int ld
     return hipErrorInvalidValue;
 }
 
+// Streaming read of n16 16-byte words: block b sums its words (grid-stride,
+// four loads in flight per thread) and writes one float, sink[b].  The
+// bandwidth ceiling the detection kernels are measured against.
+__global__ __launch_bounds__(256) void k_stream_read(const float4* __restrict__ p, int64_t n16,
+                                                     float* __restrict__ sink)
+{
+    constexpr int U = 4;
+    const int64_t stride = (int64_t)gridDim.x * 256;
+    int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    float acc = 0.0f;
+    for (; i + (U - 1) * stride < n16; i += U * stride) {
+        float4 v[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) v[u] = p[i + u * stride];
+#pragma unroll
+        for (int u = 0; u < U; ++u) acc += (v[u].x + v[u].y) + (v[u].z + v[u].w);
+    }
+    for (; i < n16; i += stride) {
+        const float4 v = p[i];
+        acc += (v.x + v.y) + (v.z + v.w);
+    }
+    __shared__ float part[4];
+    for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
+    if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) sink[blockIdx.x] = (part[0] + part[1]) + (part[2] + part[3]);
+}
+
+hipError_t launch_stream_read(const void* src, int64_t bytes, float* sink, int grid, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_stream_read, dim3(grid), dim3(256), 0, s, static_cast<const float4*>(src), bytes / 16,
+                       sink);
+    return hipGetLastError();
+}
+
 hipError_t launch_zero_i64(int64_t* p, int64_t n, hipStream_t s)
 {
     if (n <= 0) return hipSuccess;

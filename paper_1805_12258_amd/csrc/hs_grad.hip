@@ -202,9 +202,26 @@ constexpr int kFThreads = kFR * kLanes;     // 1024
 template <typename TIn> struct GIo;
 template <> struct GIo<float> {
     __device__ static float ld(const void* p, int64_t e) { return static_cast<const float*>(p)[e]; }
+    // four consecutive values at element e (16-byte aligned)
+    __device__ static void ld4(const void* p, int64_t e, float (&x)[4])
+    {
+        const float4 q = *reinterpret_cast<const float4*>(static_cast<const float*>(p) + e);
+        x[0] = q.x;
+        x[1] = q.y;
+        x[2] = q.z;
+        x[3] = q.w;
+    }
 };
 template <> struct GIo<_Float16> {
     __device__ static float ld(const void* p, int64_t e) { return (float)static_cast<const _Float16*>(p)[e]; }
+    __device__ static void ld4(const void* p, int64_t e, float (&x)[4])
+    {
+        const uint2 q = *reinterpret_cast<const uint2*>(static_cast<const _Float16*>(p) + e);
+        _Float16 h[4];
+        __builtin_memcpy(h, &q, 8);
+#pragma unroll
+        for (int v = 0; v < 4; ++v) x[v] = (float)h[v];
+    }
 };
 struct bf16_bits {
     uint16_t b;
@@ -214,18 +231,67 @@ template <> struct GIo<bf16_bits> {
     {
         return __uint_as_float((uint32_t)static_cast<const uint16_t*>(p)[e] << 16);
     }
+    __device__ static void ld4(const void* p, int64_t e, float (&x)[4])
+    {
+        const uint2 q = *reinterpret_cast<const uint2*>(static_cast<const uint16_t*>(p) + e);
+        x[0] = __uint_as_float(q.x << 16);
+        x[1] = __uint_as_float(q.x & 0xffff0000u);
+        x[2] = __uint_as_float(q.y << 16);
+        x[3] = __uint_as_float(q.y & 0xffff0000u);
+    }
 };
 
+// Rows of partial sums a 16-row tile produces for stretch factor m: the most
+// distinct floor(i/m) over kFR consecutive template indices.
+__host__ __device__ constexpr int fused_rows(int m) { return (kFR + m - 2) / m + 1; }
+__host__ __device__ inline int64_t fused_partial_offset(int m, int row_blocks, int64_t n_bt)
+{
+    int64_t o = 0;
+    for (int k = 2; k < m; ++k) o += (int64_t)row_blocks * fused_rows(k) * n_bt * stage_pitch(k);
+    return o;
+}
+
+// LDS of one tile.  gt: the tile's G_m values, one row per wave, with zero
+// bins on both sides (the first target column starts up to m - 1 bins
+// before the tile, the last one can end up to 23 bins after it for m <= 16)
+// so that the m-bin sums read zeros outside the tile instead of testing
+// bounds.
+// hr: the rows' m-bin sums (pitch stage_pitch(2), the widest), with zero
+// rows above and below for the same reason on the m-row sums: a target row
+// reaches at most m - 1 rows above the tile and 2m - 2 below.
+constexpr int kGPad = kMaxH;                       // zero bins before the tile
+constexpr int kGPadR = 2 * kMaxH;                  // and after it
+constexpr int kGPitch = kGPad + kTileBins + kGPadR;
+constexpr int kHPitch = stage_pitch(2);
+template <int H> constexpr int hr_top() { return H - 1; }
+template <int H> constexpr int hr_rows() { return kFR + 3 * H - 3; }
+
+// The weight g_k = gscale exp(HP_k / tau - lse_k) in base 2 and fp32, with
+// no fp64 operation per point: with L_k = tau lse_k / input_scale (fp64,
+// in storage units) split as L_hi + L_lo (two fp32 values, L_lo below half
+// an ulp of L_hi),
+//     log2 g_k = (HP - L_hi) c - L_lo c + log2|gscale|,  c = log2(e) / (tau scale),
+// formed as fma(HP - L_hi, c, K_k) with K_k = -L_lo c + log2|gscale| per
+// plane.  HP - L_hi is exact where HP is within a factor two of L_hi (the
+// weights that matter: lse_k is at least max HP_k / tau), and the remaining
+// roundings leave a few fp32 ulps of relative error in the exponent.  A
+// negative gscale flips the sign of the result, zero gives zero weights.
+// Up to eight planes the tile kernel keeps to 64 VGPRs so that two blocks
+// (eight waves per SIMD) share a compute unit and one block's loads overlap
+// the other's arithmetic.
+template <int H> constexpr int bwd_min_waves() { return H <= 8 ? 8 : 4; }
+
 template <typename TIn, int H>
-__global__ __launch_bounds__(kFThreads) void k_lse_bwd_tiles(const void* __restrict__ fop, int64_t ld, int T, int N,
-                                                             float inv_scale, double inv_tau,
+__global__ __launch_bounds__(kFThreads, bwd_min_waves<H>()) void k_lse_bwd_tiles(const void* __restrict__ fop, int64_t ld, int T, int N,
+                                                             double inv_scale, double tau, float c2,
                                                              const double* __restrict__ lse,
                                                              const double* __restrict__ gscale_p,
                                                              float* __restrict__ dfop, float* __restrict__ part,
                                                              int row_blocks, int n_bt)
 {
-    __shared__ float tile[kFR * kTileBins];
-    __shared__ float hrow[kFR * stage_pitch(2)];     // row sums over each target's bins
+    __shared__ __align__(16) float gt[kFR * kGPitch];
+    __shared__ float hr[hr_rows<H>() * kHPitch];
+    __shared__ float lsplit[2 * H];                  // L_hi, K of every plane
     const int rb = blockIdx.x / n_bt;
     const int bt = blockIdx.x - rb * n_bt;
     const int r0 = rb * kFR;
@@ -237,35 +303,68 @@ __global__ __launch_bounds__(kFThreads) void k_lse_bwd_tiles(const void* __restr
     const int rr = threadIdx.x >> 6;            // row of the tile (the wave)
     const int r = r0 + rr;
     const bool row_ok = rr < nr;
-    const float gsc = gscale_p ? (float)*gscale_p : 1.0f;
+    const bool full = row_ok && nb == kTileBins;
+    const double gsc = gscale_p ? *gscale_p : 1.0;
+    if (threadIdx.x < H) {
+        const double L = tau * lse[threadIdx.x] / inv_scale;
+        const float hi = (float)L;
+        const float lo = (float)(L - (double)hi);
+        lsplit[2 * threadIdx.x] = hi;
+        lsplit[2 * threadIdx.x + 1] = (float)(-(double)lo * (double)c2 + log2(fabs(gsc)));
+    }
+    // zero pads (never written afterwards)
+    for (int e = threadIdx.x; e < kFR * (kGPad + kGPadR); e += kFThreads) {
+        const int row = e / (kGPad + kGPadR), q = e - row * (kGPad + kGPadR);
+        gt[row * kGPitch + (q < kGPad ? q : kTileBins + q)] = 0.0f;
+    }
+    for (int e = threadIdx.x; e < hr_rows<H>() * kHPitch; e += kFThreads) hr[e] = 0.0f;
 
     // weights of every plane at the thread's four points (0 outside the plane)
     float G[H][kV];
     {
-        // every source value first (unconditional loads at clamped indices,
-        // so that all of them are in flight together), then the sums
+        // every source value first (all loads in flight together), then the
+        // sums.  Plane 1: the thread's four values (one 16-byte load in a
+        // full tile).  m >= 2: the four bins j .. j+3 read elements
+        // floor(j/m) and at most one more, so two loads and a select.
+        const int jl = j0 + kV * lane;
+        const int jc = min(jl, N - 1);                 // lanes past the end read a valid element
+        {
+            const int64_t rowe = (int64_t)(row_ok ? r : 0) * ld;
+            if (nb == kTileBins) {
+                GIo<TIn>::ld4(fop, rowe + jl, G[0]);
+            } else {
 #pragma unroll
-        for (int k = 1; k <= H; ++k) {
-            const int sr = row_ok ? floordiv32(r - c, k) + c : 0;
-#pragma unroll
-            for (int v = 0; v < kV; ++v) {
-                const int jj = kV * lane + v < nb ? j0 + kV * lane + v : j0;
-                G[k - 1][v] = GIo<TIn>::ld(fop, (int64_t)sr * ld + jj / k);
+                for (int v = 0; v < kV; ++v) G[0][v] = GIo<TIn>::ld(fop, rowe + min(jl + v, N - 1));
             }
         }
+        static_for<2, H>([&](auto mc) {
+            constexpr int m = decltype(mc)::value;
+            const int sr = row_ok ? floordiv32(r - c, m) + c : 0;
+            const int e0 = jc / m;
+            const int e1 = min(e0 + 1, (N - 1) / m);
+            const float x0 = GIo<TIn>::ld(fop, (int64_t)sr * ld + e0);
+            const float x1 = GIo<TIn>::ld(fop, (int64_t)sr * ld + e1);
+            const int split = m * (e0 + 1) - jc;           // bins v < split read element e0
+#pragma unroll
+            for (int v = 0; v < kV; ++v) G[m - 1][v] = v < split ? x0 : x1;
+        });
+        __syncthreads();                               // split exponents and zero pads are in LDS
         float acc[kV];
 #pragma unroll
         for (int k = 1; k <= H; ++k) {
+            const float lhi = lsplit[2 * (k - 1)], kk = lsplit[2 * (k - 1) + 1];
+#pragma unroll
+            for (int v = 0; v < kV; ++v) {
+                acc[v] = k == 1 ? G[0][v] : acc[v] + G[k - 1][v];
+                G[k - 1][v] = __builtin_amdgcn_exp2f(__builtin_fmaf(acc[v] - lhi, c2, kk));
+            }
+        }
+        if (!full) {
 #pragma unroll
             for (int v = 0; v < kV; ++v) {
                 const bool ok = row_ok && kV * lane + v < nb;
-                const float x = G[k - 1][v];
-                acc[v] = k == 1 ? x : acc[v] + x;
-                const float hp = acc[v] * inv_scale;
-                // the exponent HP/tau - lse in fp64 (both terms can be large),
-                // then exp through the hardware exp2 on the fp32 difference
-                const float d = (float)((double)hp * inv_tau - lse[k - 1]);
-                G[k - 1][v] = ok ? gsc * __builtin_amdgcn_exp2f(d * 1.4426950408889634f) : 0.0f;
+#pragma unroll
+                for (int k = 0; k < H; ++k) G[k][v] = ok ? G[k][v] : 0.0f;
             }
         }
     }
@@ -275,46 +374,56 @@ __global__ __launch_bounds__(kFThreads) void k_lse_bwd_tiles(const void* __restr
 #pragma unroll
         for (int v = 0; v < kV; ++v) G[m - 1][v] = G[m - 1][v] + G[m][v];
     }
-    if (row_ok) {
-        float* dst = dfop + (int64_t)r * N + j0;
+    if (gsc < 0.0) {
 #pragma unroll
-        for (int v = 0; v < kV; ++v)
-            if (kV * lane + v < nb) dst[kV * lane + v] = G[0][v];
+        for (int m = 0; m < H; ++m)
+#pragma unroll
+            for (int v = 0; v < kV; ++v) G[m][v] = -G[m][v];
     }
-    // box sums of G_m, m >= 2, inside the tile: first each row's sums over
-    // the m bins of every target column, then each target's sum over its m
-    // rows (m is a compile-time constant here: the short loops unroll)
+    if (row_ok) {
+        float* dst = dfop + (int64_t)r * N + j0 + kV * lane;
+        if (full && (N & 3) == 0 && (reinterpret_cast<uintptr_t>(dfop) & 15) == 0) {
+            *reinterpret_cast<float4*>(dst) = make_float4(G[0][0], G[0][1], G[0][2], G[0][3]);
+        } else {
+#pragma unroll
+            for (int v = 0; v < kV; ++v)
+                if (kV * lane + v < nb) dst[v] = G[0][v];
+        }
+    }
+    // box sums of G_m, m >= 2, inside the tile: each wave sums its own row
+    // over the m bins of every target column (no barrier: it reads back
+    // what it wrote), then each target's sum over its m rows; the zero pads
+    // stand for everything outside the tile
+    float* const grow = gt + rr * kGPitch + kGPad;
     static_for<2, H>([&](auto mc) {
         constexpr int m = decltype(mc)::value;
-        constexpr int NR = stage_rows(m), P = stage_pitch(m);
-        __syncthreads();               // the previous factor's sums are done
+        constexpr int NR = fused_rows(m), P = stage_pitch(m);
+        *reinterpret_cast<float4*>(grow + kV * lane) = make_float4(G[m - 1][0], G[m - 1][1], G[m - 1][2], G[m - 1][3]);
+        // the wave reads back bins its other lanes wrote: keep the order
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        const int jfirst = m * (j0 / m) - j0;          // first target's first bin, in (-m, 0]
+        if (m > 2) __syncthreads();                    // the previous factor's row sums are read
 #pragma unroll
-        for (int v = 0; v < kV; ++v) tile[rr * kTileBins + kV * lane + v] = G[m - 1][v];
-        __syncthreads();
-        const int blo = j0 / m;
-        for (int e = threadIdx.x; e < nr * P; e += kFThreads) {
-            const int rw = e / P, tc = e - rw * P;
-            const int jbase = m * (blo + tc) - j0;
-            float acc = 0.0f;
+        for (int tc = lane; tc < P + 63 - (P + 63) % 64; tc += 64) {
+            if (tc < P) {
+                const float* src = grow + jfirst + m * tc;
+                float acc = src[0];
 #pragma unroll
-            for (int dc = 0; dc < m; ++dc) {
-                const int j = jbase + dc;
-                if (j >= 0 && j < nb) acc += tile[rw * kTileBins + j];
+                for (int dc = 1; dc < m; ++dc) acc += src[dc];
+                hr[(hr_top<H>() + rr) * kHPitch + tc] = acc;
             }
-            hrow[rw * P + tc] = acc;
         }
         __syncthreads();
-        const int lo = src_row(r0, m, c);
-        float* out = part + partial_offset(m, row_blocks, n_bt) + (((int64_t)rb * NR) * n_bt + bt) * P;
+        const int rfirst = c + m * (src_row(r0, m, c) - c) - r0;   // first target's first row, in (-m, 0]
+        float* out = part + fused_partial_offset(m, row_blocks, n_bt) + (((int64_t)rb * NR) * n_bt + bt) * P;
         for (int e = threadIdx.x; e < NR * P; e += kFThreads) {
             const int tr = e / P, tc = e - tr * P;
-            const int rbase = c + m * (lo + tr - c) - r0;
-            float acc = 0.0f;
+            const float* src = hr + (hr_top<H>() + rfirst + m * tr) * kHPitch + tc;
+            float acc = src[0];
 #pragma unroll
-            for (int dr = 0; dr < m; ++dr) {
-                const int rw = rbase + dr;
-                if (rw >= 0 && rw < nr) acc += hrow[rw * P + tc];
-            }
+            for (int dr = 1; dr < m; ++dr) acc += src[dr * kHPitch];
             out[(int64_t)tr * n_bt * P + tc] = acc;
         }
     });
@@ -341,10 +450,10 @@ __global__ __launch_bounds__(256) void k_bwd_reduce_t(float* __restrict__ dfop, 
         bool any = false;
         static_for<2, H>([&](auto mc) {
             constexpr int m = decltype(mc)::value;
-            constexpr int NR = stage_rows(m), P = stage_pitch(m);
+            constexpr int NR = fused_rows(m), P = stage_pitch(m);
             const int first = max(c + m * (a - c), 0), last = min(c + m * (a - c) + m - 1, T - 1);
             if (first > last) return;
-            const float* pm = part + partial_offset(m, row_blocks, n_bt);
+            const float* pm = part + fused_partial_offset(m, row_blocks, n_bt);
             for (int rb = first / R; rb <= last / R; ++rb) {
                 const int tr = a - src_row(rb * R, m, c);
 #pragma unroll
@@ -520,7 +629,7 @@ hipError_t launch_lse_backward_fused(int dtype, const void* fop, int64_t ld, int
     const int64_t tiles = (int64_t)row_blocks * n_bt;
     if (tiles > 0x7fffffff || H < 1 || H > kMaxH) return hipErrorInvalidValue;
     const dim3 g((unsigned)tiles), b(kFThreads);
-    const double it = 1.0 / tau;
+    const float c2 = (float)(1.4426950408889634 * (double)inv_scale / tau);   // log2(e) / (tau scale)
     bool ok = false;
     static_for<1, kMaxH>([&](auto hc) {
         constexpr int HH = decltype(hc)::value;
@@ -528,16 +637,16 @@ hipError_t launch_lse_backward_fused(int dtype, const void* fop, int64_t ld, int
         ok = true;
         switch (dtype) {
         case HS_DTYPE_F32:
-            hipLaunchKernelGGL((k_lse_bwd_tiles<float, HH>), g, b, 0, s, fop, ld, T, (int)N, inv_scale, it, lse,
+            hipLaunchKernelGGL((k_lse_bwd_tiles<float, HH>), g, b, 0, s, fop, ld, T, (int)N, (double)inv_scale, tau, c2, lse,
                                gscale, dfop, part, row_blocks, n_bt);
             break;
         case HS_DTYPE_F16:
-            hipLaunchKernelGGL((k_lse_bwd_tiles<_Float16, HH>), g, b, 0, s, fop, ld, T, (int)N, inv_scale, it, lse,
+            hipLaunchKernelGGL((k_lse_bwd_tiles<_Float16, HH>), g, b, 0, s, fop, ld, T, (int)N, (double)inv_scale, tau, c2, lse,
                                gscale, dfop, part, row_blocks, n_bt);
             break;
         case HS_DTYPE_BF16:
-            hipLaunchKernelGGL((k_lse_bwd_tiles<bf16_bits, HH>), g, b, 0, s, fop, ld, T, (int)N, inv_scale, it,
-                               lse, gscale, dfop, part, row_blocks, n_bt);
+            hipLaunchKernelGGL((k_lse_bwd_tiles<bf16_bits, HH>), g, b, 0, s, fop, ld, T, (int)N, (double)inv_scale, tau,
+                               c2, lse, gscale, dfop, part, row_blocks, n_bt);
             break;
         default:
             ok = false;

@@ -273,6 +273,7 @@ hipError_t launch_fused(int mode, int dtype, int H, const TileArgs& a, int64_t n
                         int grid, int lds_bytes, hipStream_t s);
 hipError_t launch_batched(int dtype, int H, const BatchArgs& a, int grid, int lds_bytes,
                           hipStream_t s);
+hipError_t launch_stream_read(const void* src, int64_t bytes, float* sink, int grid, hipStream_t s);
 hipError_t launch_zero_i64(int64_t* p, int64_t n, hipStream_t s);
 
 // Bounded per-plane selection (policies of hs_select, n_cand <= kSelLdsCand).

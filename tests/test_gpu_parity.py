@@ -433,3 +433,19 @@ def test_walk_bins_per_lane(V, name, dtype, H):
     assert plan.info["detector"] == 1 and plan.info["bins_per_lane"] == V
     got = gpu_detect(plan, dev, ta, capacity=H * T * N)
     assert_same_candidates(got, oracle_detect_sorted(store, H, ta, scale=scale))
+
+
+@pytest.mark.parametrize("n,grid", [(4 * 250007, 64), (4 * 250007, 8192), (4, 1), (1 << 22, 4096)])
+def test_stream_read_sum(n, grid):
+    """The read-ceiling kernel reads every word once: the block sums add up
+    to the buffer's sum (fp64 reference, fp32 rounding tolerance), blocks
+    past the data write zero."""
+    print("case", n, grid, flush=True)
+    g = torch.Generator().manual_seed(n + grid)
+    x = torch.rand(n, generator=g, dtype=torch.float32)
+    sink = torch.full((grid,), float("nan"), dtype=torch.float32, device="cuda")
+    hs.hs_stream_read(x.cuda(), 4 * n, sink, grid)
+    s = sink.cpu().double()
+    assert torch.isfinite(s).all()
+    ref = x.double().sum().item()
+    assert abs(s.sum().item() - ref) <= 1e-5 * ref + 1e-6

@@ -130,6 +130,11 @@ def test_null_arguments_rejected_without_gpu():
     pb = hs.Plan(21, 0, 8, n_chans=[100, 200])
     assert hs._c_hs_detect(pb.handle, ctypes.c_void_p(0x1000), 1000, out, out, 1, out,
                            null) == hs.HS_ERR_INVALID
+    # the read-ceiling kernel: size, alignment and grid checked on the host
+    src = ctypes.c_void_p(0x1000)
+    for a, nb, gr in ((null, 16, 1), (src, 0, 1), (src, 24, 1), (fake, 16, 1), (src, 16, 0),
+                      (src, 16, 65537)):
+        assert hs._c_hs_stream_read(a, nb, out, gr, null) == hs.HS_ERR_INVALID
 
 
 @pytest.mark.parametrize("T,N", [(85, 1 << 21), (21, 1 << 16), (64, 4097), (85, 3000), (5, 256 * 9),
