@@ -112,7 +112,7 @@ hipError_t sel_layout(int64_t n, int end_bit, SelLayout& L)
 // ---- bounded selection -----------------------------------------------------
 
 constexpr int kST = 1024;               // threads per block of the selection passes
-constexpr int kMaxSelBlocks = 32;       // blocks of the passes over the whole list
+constexpr int kMaxSelBlocks = 64;       // blocks of the passes over the whole list
 constexpr int kSelLdsBnd = 2048;        // boundary entries sorted in LDS at once
 constexpr int kSelU = 8;                // loads in flight per thread (the passes are latency-bound)
 constexpr int kHistWords = 8192;        // per-block LDS histogram: H planes x bins(H)
@@ -163,9 +163,12 @@ struct alignas(128) PlaneInfo {   // one cache line each: the passes' atomics on
     uint32_t n_sel, n_bnd;    // collected so far (global counters)
 };
 
+// Blocks over a list of n entries: one round of kSelU loads per thread
+// covers kSelU * kST entries, so up to 64 such chunks each pass takes a
+// single round of loads.
 int sel_blocks(int64_t n)
 {
-    const int64_t b = (n + 16383) / 16384;
+    const int64_t b = (n + (int64_t)kSelU * kST - 1) / ((int64_t)kSelU * kST);
     return (int)(b < 1 ? 1 : (b > kMaxSelBlocks ? kMaxSelBlocks : b));
 }
 
@@ -257,24 +260,41 @@ __global__ __launch_bounds__(kST) void k_sel_stats(const uint64_t* __restrict__ 
     }
 }
 
-// The planes' ranges and runs from the blocks' statistics (thread q < H
-// works out plane q) into `pi` (LDS).
+// The planes' ranges and runs from the blocks' statistics into `pi` (LDS):
+// every (block, plane) record is loaded by its own thread (one round of
+// loads), then thread q < H works out plane q from LDS.  Called by the
+// whole block (contains barriers).
 __device__ void plane_infos(const uint32_t* __restrict__ cnt, const uint64_t* __restrict__ kmin,
                             const uint64_t* __restrict__ kmax, int G, int H, PlaneInfo* pi)
 {
-    const int q = threadIdx.x;
+    __shared__ uint32_t sc[kMaxSelBlocks * kMaxH];
+    __shared__ uint64_t sl[kMaxSelBlocks * kMaxH], sh[kMaxSelBlocks * kMaxH];
+    __shared__ uint32_t tot[kMaxH];
+    const int t = threadIdx.x;
+    if (t < G * H) {
+        sc[t] = cnt[t];
+        sl[t] = kmin[t];
+        sh[t] = kmax[t];
+    }
+    __syncthreads();
+    const int q = t;
+    uint32_t total = 0;
+    uint64_t lo = ~0ull, hi = 0;
     if (q < H) {
-        uint32_t before = 0, total = 0;
-        uint64_t lo = ~0ull, hi = 0;
         for (int b = 0; b < G; ++b) {
-            for (int p = 0; p < q; ++p) before += cnt[(int64_t)b * H + p];
-            const int64_t o = (int64_t)b * H + q;
-            total += cnt[o];
-            if (cnt[o]) {
-                lo = kmin[o] < lo ? kmin[o] : lo;
-                hi = kmax[o] > hi ? kmax[o] : hi;
+            const int o = b * H + q;
+            total += sc[o];
+            if (sc[o]) {
+                lo = sl[o] < lo ? sl[o] : lo;
+                hi = sh[o] > hi ? sh[o] : hi;
             }
         }
+        tot[q] = total;
+    }
+    __syncthreads();
+    if (q < H) {
+        uint32_t before = 0;
+        for (int p = 0; p < q; ++p) before += tot[p];
         PlaneInfo x{};
         x.lo = lo;
         x.hi = hi;
@@ -322,17 +342,32 @@ __global__ __launch_bounds__(kST) void k_sel_cut(const uint32_t* __restrict__ ph
     __shared__ uint32_t h[1024];
     const int k = blockIdx.x, t = threadIdx.x;
     const int bins = sel_bins(H);
+    __shared__ uint32_t wsum[kST / 64];
+    // the blocks' counts of bin t, sixteen loads in flight at a time
     uint32_t own = 0;
-    if (t < bins)
-        for (int b = 0; b < G; ++b) own += ph[((int64_t)b * H + k) * bins + t];
-    h[t] = t < bins ? own : 0u;
-    __syncthreads();
-    for (int d = 1; d < 1024; d <<= 1) {
-        const uint32_t add = t + d < 1024 ? h[t + d] : 0u;
-        __syncthreads();
-        h[t] += add;
-        __syncthreads();
+    if (t < bins) {
+        constexpr int U = 16;
+        for (int b0 = 0; b0 < G; b0 += U) {
+            uint32_t x[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) x[u] = b0 + u < G ? ph[((int64_t)(b0 + u) * H + k) * bins + t] : 0u;
+#pragma unroll
+            for (int u = 0; u < U; ++u) own += x[u];
+        }
     }
+    // suffix sums over the bins: within each wave by shuffles, then across
+    // the waves
+    const int lane = t & 63, w = t >> 6;
+    uint32_t suf = own;
+    for (int d = 1; d < 64; d <<= 1) {
+        const uint32_t y = (uint32_t)__shfl_down((int)suf, d, 64);
+        if (lane + d < 64) suf += y;
+    }
+    if (lane == 0) wsum[w] = suf;
+    __syncthreads();
+    for (int v = w + 1; v < kST / 64; ++v) suf += wsum[v];
+    h[t] = suf;
+    __syncthreads();
     const uint32_t m = info[k].count;
     if (t == 0) {
         info[k].n_sel = 0;
@@ -346,8 +381,7 @@ __global__ __launch_bounds__(kST) void k_sel_cut(const uint32_t* __restrict__ ph
         }
         return;
     }
-    const uint32_t suf = h[t];                   // entries in bins t..end
-    const uint32_t next = t < 1023 ? h[t + 1] : 0u;
+    const uint32_t next = t < 1023 ? h[t + 1] : 0u;   // suf: entries in bins t..end
     if (suf >= (uint32_t)n_cand && next < (uint32_t)n_cand) {
         info[k].cut = t;
         info[k].above = next;
@@ -376,19 +410,13 @@ __global__ __launch_bounds__(kST) void k_sel_collect(const uint64_t* __restrict_
     int64_t e0, e1;
     chunk_of(n, e0, e1);
     auto bin_of = [&](uint64_t x, uint32_t k) { return (int64_t)((sel_key(x, cfg) - pi[k].lo) >> pi[k].shift); };
-    for_entries(cand, e0, e1, [&](uint64_t x) {
+    auto count = [&](uint64_t x) {
         const uint32_t k = ((uint32_t)x >> cfg.s_bin) & kmask;
         const int64_t d = bin_of(x, k);
         if (d > pi[k].cut) atomicAdd(&na[k], 1u);
         else if (d == pi[k].cut) atomicAdd(&nb[k], 1u);
-    });
-    __syncthreads();
-    if (t < H) {
-        base_a[t] = na[t] ? atomicAdd(&info[t].n_sel, na[t]) : 0u;
-        base_b[t] = nb[t] ? atomicAdd(&info[t].n_bnd, nb[t]) : 0u;
-    }
-    __syncthreads();
-    for_entries(cand, e0, e1, [&](uint64_t x) {
+    };
+    auto place = [&](uint64_t x) {
         const uint32_t k = ((uint32_t)x >> cfg.s_bin) & kmask;
         const int64_t d = bin_of(x, k);
         if (d > pi[k].cut) {
@@ -398,7 +426,35 @@ __global__ __launch_bounds__(kST) void k_sel_collect(const uint64_t* __restrict_
             const uint32_t p = base_b[k] + atomicAdd(&ib[k], 1u);
             if (p < pi[k].count) bnd[pi[k].start + p] = x;
         }
-    });
+    };
+    auto reserve = [&]() {
+        __syncthreads();
+        if (t < H) {
+            base_a[t] = na[t] ? atomicAdd(&info[t].n_sel, na[t]) : 0u;
+            base_b[t] = nb[t] ? atomicAdd(&info[t].n_bnd, nb[t]) : 0u;
+        }
+        __syncthreads();
+    };
+    if (e1 - e0 <= (int64_t)kSelU * kST) {
+        // one round of loads: the entries stay in registers for both passes
+        uint64_t x[kSelU];
+#pragma unroll
+        for (int u = 0; u < kSelU; ++u) {
+            const int64_t e = e0 + t + (int64_t)u * kST;
+            x[u] = e < e1 ? cand[e] : 0ull;
+        }
+#pragma unroll
+        for (int u = 0; u < kSelU; ++u)
+            if (e0 + t + (int64_t)u * kST < e1) count(x[u]);
+        reserve();
+#pragma unroll
+        for (int u = 0; u < kSelU; ++u)
+            if (e0 + t + (int64_t)u * kST < e1) place(x[u]);
+    } else {
+        for_entries(cand, e0, e1, count);
+        reserve();
+        for_entries(cand, e0, e1, place);
+    }
 }
 
 // Rank of each of n distinct keys in LDS (descending: the number of larger
