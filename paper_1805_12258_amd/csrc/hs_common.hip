@@ -35,11 +35,13 @@ __global__ void k_zero_i64(int64_t* p, int64_t n)
 // histogram of the plane field over the first min(total, capacity) entries
 // of each list.  Grid (x, lists); a list whose total is ~0 (a FOP the
 // batched detection rejected) is left as it is.  The list is short (a few
-// MB at most) and latency-bound: each thread keeps kPcU loads in flight and
-// counts per plane in registers, and few blocks take part, so that few
-// atomics meet on the counts' cache line.
+// MB at most) and latency-bound: each thread keeps kPcU loads in flight (24
+// blocks cover 384 K entries in one round), every entry is one LDS atomic on
+// the block's histogram, and few blocks take part, so that few atomics meet
+// on the counts' cache line.
 constexpr int kPcThreads = 1024;
-constexpr int kPcU = 8;
+constexpr int kPcU = 16;
+constexpr int kPcMaxBlocks = 24;
 
 __global__ __launch_bounds__(kPcThreads) void k_plane_counts(const uint64_t* out, const int64_t* out_offsets,
                                                              const int64_t* caps, int64_t cap1,
@@ -55,9 +57,7 @@ __global__ __launch_bounds__(kPcThreads) void k_plane_counts(const uint64_t* out
     if (tot == ~0ull) return;
     const int64_t n = (int64_t)tot < cap ? (int64_t)tot : cap;
     if (threadIdx.x < kMaxH) hist[threadIdx.x] = 0;
-    uint32_t cnt[kMaxH];
-#pragma unroll
-    for (int k = 0; k < kMaxH; ++k) cnt[k] = 0;
+    __syncthreads();
     const int64_t stride = (int64_t)gridDim.x * kPcThreads;
     for (int64_t e0 = blockIdx.x * (int64_t)kPcThreads + threadIdx.x; e0 < n; e0 += stride * kPcU) {
         // unconditional loads (indexes clamped into the list), so that all
@@ -69,26 +69,8 @@ __global__ __launch_bounds__(kPcThreads) void k_plane_counts(const uint64_t* out
             w[u] = (uint32_t)o[e < n ? e : n - 1];
         }
 #pragma unroll
-        for (int u = 0; u < kPcU; ++u) {
-            const uint32_t k = e0 + u * stride < n ? (w[u] >> s_bin) & kmask : (uint32_t)kMaxH;
-#pragma unroll
-            for (int q = 0; q < kMaxH; ++q) cnt[q] += k == (uint32_t)q ? 1u : 0u;
-        }
-    }
-    // wave sums, then one LDS atomic per wave and plane
-    const int lane = threadIdx.x & 63;
-#pragma unroll
-    for (int q = 0; q < kMaxH; ++q) {
-        uint32_t v = cnt[q];
-#pragma unroll
-        for (int d = 32; d >= 1; d >>= 1) v += (uint32_t)__shfl_xor((int)v, d, 64);
-        cnt[q] = v;
-    }
-    __syncthreads();
-    if (lane == 0) {
-#pragma unroll
-        for (int q = 0; q < kMaxH; ++q)
-            if (cnt[q]) atomicAdd(&hist[q], cnt[q]);
+        for (int u = 0; u < kPcU; ++u)
+            if (e0 + u * stride < n) atomicAdd(&hist[(w[u] >> s_bin) & kmask], 1u);
     }
     __syncthreads();
     if (threadIdx.x < H && hist[threadIdx.x]) atomicAdd(&c[threadIdx.x], (unsigned long long)hist[threadIdx.x]);
@@ -99,11 +81,12 @@ hipError_t launch_plane_counts(const hs_cand* out, const int64_t* out_offsets, c
                                hipStream_t s)
 {
     if (n_lists < 1 || n_lists > 65535 || H < 1 || H > kMaxH) return hipErrorInvalidValue;
-    // one list: enough blocks for its capacity, at most 16; a batch: one block per list
+    // one list: enough blocks for its capacity, at most kPcMaxBlocks; a
+    // batch: one block per list
     int64_t bx = 1;
     if (n_lists == 1) {
         bx = (cap + (int64_t)kPcThreads * kPcU - 1) / ((int64_t)kPcThreads * kPcU);
-        bx = bx < 1 ? 1 : (bx > 16 ? 16 : bx);
+        bx = bx < 1 ? 1 : (bx > kPcMaxBlocks ? kPcMaxBlocks : bx);
     }
     hipLaunchKernelGGL(k_plane_counts, dim3((unsigned)bx, (unsigned)n_lists), dim3(kPcThreads), 0, s,
                        reinterpret_cast<const uint64_t*>(out), out_offsets, caps, cap, counts, H, s_bin, kmask);
