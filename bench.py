@@ -18,8 +18,10 @@ reports it with its margins under `autotuned`.
 Prints one JSON line.  `value` is FOP points per second (every point taken
 through all 8 planes and the threshold test).  `roofline` refers to the
 detection kernel the chosen plan launches: algorithmic bytes (one read of
-the FOP + 8 bytes per candidate + the counters) over its average launch
-time, measured with HIP events on the launch stream.  `traffic` comes from
+the FOP + 8 bytes per candidate + the counters) over the average duration
+of one hs_detect call (the counter clear, the detection kernel and the
+per-plane counting pass), measured with HIP events on the launch stream.
+`cold_start` times the process's first 60 launches.  `traffic` comes from
 rocprofv3 FETCH_SIZE / WRITE_SIZE counters recorded in profiles/ for that
 kernel and its current sources (null otherwise).  `read_ceiling` times one
 streaming read of the plane (hs_stream_read), the bound the detection
@@ -655,6 +657,7 @@ def main():
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "kernel": kname, "launch_ms": r["launch_ms"],
+                     "launch": "one hs_detect call: k_zero_i64 + %s + k_plane_counts" % kname,
                      "algorithmic_bytes": alg_bytes},
         "autotuned": tuned,
         "cold_start": cold,
@@ -777,6 +780,19 @@ def main():
             del store
         line["variants"] = var
         log("variants done")
+
+    if not args.no_variants:
+        # the fractional m/k mapping on the same plane (k source points per
+        # point of plane k, 36 at H = 8)
+        pf = hs.Plan(T, N, H, mapping="fractional")
+        rf = time_detect(pf, fop, ta, capacity, max(10, args.steps // 10), 3)
+        abf = points * 4 + 8 * int(rf["counts"][-1]) + 8 * (H + 1)
+        line["fractional"] = {"ms_per_step": rf["ms_per_step"], "launch_ms": rf["launch_ms"],
+                              "value": points / (rf["ms_per_step"] * 1e-3), "unit": "points/s",
+                              "gathers_per_point": H * (H + 1) // 2, "candidates": int(rf["counts"][-1]),
+                              "hbm_gbs": abf / (rf["launch_ms"] * 1e-3) / 1e9,
+                              "kernel": detection_kernel(pf)[0]}
+        log("fractional: %.3f ms" % rf["ms_per_step"])
 
     if args.batched_fops > 0:
         del fop, ref_out
