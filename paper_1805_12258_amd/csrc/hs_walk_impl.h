@@ -68,8 +68,11 @@ template <> struct St<bf16> {
 
 // Bins of a strip for V bins per lane.
 __host__ __device__ constexpr int strip_bins(int V) { return 64 * V; }
-// Per-wave candidate buffer: room for the V * 64 hits one call can add.
-__host__ __device__ constexpr int cand_cap(int V) { return 64 * V > 320 ? 64 * V : 320; }
+// Per-wave candidate buffer (entries).  One emission call adds at most 64
+// hits per bin of the lane group; the buffer is written out before a bin's
+// hits when they might not fit, so the size is free: 320 entries, or 128
+// with eight bins per lane, whose larger rings leave less LDS per wave.
+__host__ __device__ constexpr int cand_cap(int V) { return V >= 8 ? 128 : 320; }
 
 // Elements of one source slot of stretch factor m: the range
 // [floor(j0/m), floor((j0+B-1)/m)] (at most floor((B-1)/m) + 2 elements)
@@ -340,7 +343,8 @@ struct Walker {
 
 // Occupancy asked of the compiler: with 16-bit storage and four bins per
 // lane a block's LDS leaves room for six waves per SIMD up to eight planes,
-// which holds without scratch.
+// which holds without scratch.  (Five waves at eight bins per lane would
+// spill at seven and eight planes.)
 template <typename TIn, int H, int V>
 constexpr int walk_min_waves() { return (sizeof(TIn) == 2 && H <= 8 && V == 4) ? 6 : 1; }
 
@@ -564,19 +568,22 @@ __global__ __launch_bounds__(walk::kWThreads, (walk_min_waves<TIn, H, V>())) voi
 
     // hits of plane k among the lane's values (the rare path, whole wave);
     // `lanes` lanes have one, so the call adds at most V * lanes entries.
-    // The buffer is written out only when that many might not fit, so that a
-    // flush carries a nearly full buffer (each flush costs one atomic on the
-    // list's shared counter).
-    static_assert(CAP >= B, "candidate buffer");
+    // The buffer is written out only when that many might not fit (so that a
+    // flush carries a nearly full buffer: each flush costs one atomic on the
+    // list's shared counter), or, when V * 64 entries exceed the buffer,
+    // before a bin whose hits might not fit.
+    static_assert(CAP >= 64, "candidate buffer");
+    constexpr bool kWhole = V * 64 <= CAP;
     auto emit = [&](auto kc, const float (&acc)[V], float tk, int r, int lanes) __attribute__((always_inline)) {
         constexpr int k = decltype(kc)::value;
         const uint32_t hi = ((uint32_t)r << a.s_row) | ((uint32_t)(k - 1) << a.s_bin);
-        if (ncand + V * lanes > CAP) flush();
+        if (kWhole && ncand + V * lanes > CAP) flush();
 #pragma unroll
         for (int v = 0; v < V; ++v) {
             const bool hit = acc[v] > tk;
             const uint64_t mk = __builtin_amdgcn_ballot_w64(hit);
             if (mk) {
+                if (!kWhole && ncand + __builtin_popcountll(mk) > CAP) flush();
                 const int pre = (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(mk >> 32),
                                                                __builtin_amdgcn_mbcnt_lo((uint32_t)mk, 0));
                 const float pw = EB == 4 ? acc[v] : acc[v] * a.inv_scale;   // unscaled power

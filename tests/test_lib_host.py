@@ -188,6 +188,10 @@ def test_detector_choice():
         p = hs.Plan(85, N, 8, schedule=4, bins_per_lane=V)
         assert p.info["bins_per_lane"] == V and p.info["detector"] == 1
     assert hs.Plan(85, N, 8, bins_per_lane=8).info["bins_per_lane"] == 0   # tile kernel: no walk
+    # planner's V: eight for 16-bit storage up to eight planes, else four
+    assert hs.Plan(85, N, 8, dtype="f16", input_scale=0.125).info["bins_per_lane"] == 8
+    assert hs.Plan(85, N, 9, dtype="bf16", input_scale=0.125).info["bins_per_lane"] == 4
+    assert hs.Plan(85, N, 16).info["bins_per_lane"] == 4
     for bad in (1, 3, 16, -2):
         with pytest.raises(hs.HsError):
             hs.Plan(85, N, 8, bins_per_lane=bad)
