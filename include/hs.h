@@ -108,7 +108,8 @@ typedef struct hs_plan_desc {
     int32_t mapping;           /* hs_mapping (0 = HS_MAP_PAPER)                  */
     int32_t bins_per_lane;     /* tuning: bins per lane V of the strip walk (2,  */
                                /* 4 or 8: strips of 64 V bins); 0 = planner (8  */
-                               /* for 16-bit storage up to 8 planes, else 4)    */
+                               /* for 16-bit storage up to 8 planes and for     */
+                               /* batches, else 4)                              */
 } hs_plan_desc;
 
 /* Geometry chosen by the planner (host values; no GPU needed). */

@@ -419,8 +419,10 @@ hs_status hs_plan_create(hs_plan** out, const hs_plan_desc* d)
         p->mapping = d->mapping;
         // bins per lane of the strip walk: eight for 16-bit storage up to
         // eight planes (the rings of 512-bin strips still leave four waves
-        // per SIMD), else four
-        p->walk_v = d->bins_per_lane ? d->bins_per_lane : (d->dtype != HS_DTYPE_F32 && d->n_hp <= 8 ? 8 : 4);
+        // per SIMD) and for batches (measured faster at H = 16, fp32), else
+        // four
+        p->walk_v = d->bins_per_lane ? d->bins_per_lane
+                                     : ((d->dtype != HS_DTYPE_F32 && d->n_hp <= 8) || d->n_fops > 0 ? 8 : 4);
         p->T = d->n_temp;
         p->H = d->n_hp;
         p->dtype = d->dtype;

@@ -192,6 +192,7 @@ def test_detector_choice():
     assert hs.Plan(85, N, 8, dtype="f16", input_scale=0.125).info["bins_per_lane"] == 8
     assert hs.Plan(85, N, 9, dtype="bf16", input_scale=0.125).info["bins_per_lane"] == 4
     assert hs.Plan(85, N, 16).info["bins_per_lane"] == 4
+    assert hs.Plan(85, 0, 16, n_chans=[1 << 19, 1 << 20]).info["bins_per_lane"] == 8
     for bad in (1, 3, 16, -2):
         with pytest.raises(hs.HsError):
             hs.Plan(85, N, 8, bins_per_lane=bad)
