@@ -70,9 +70,11 @@ template <> struct St<bf16> {
 __host__ __device__ constexpr int strip_bins(int V) { return 64 * V; }
 // Per-wave candidate buffer (entries).  One emission call adds at most 64
 // hits per bin of the lane group; the buffer is written out before a bin's
-// hits when they might not fit, so the size is free: 320 entries, or 128
-// with eight bins per lane, whose larger rings leave less LDS per wave.
-__host__ __device__ constexpr int cand_cap(int V) { return V >= 8 ? 128 : 320; }
+// hits when they might not fit, so it need not hold the 64 V hits of a
+// whole call.  Fewer entries would leave more LDS for waves but flush more
+// often, and a flush drains the wave's loads in flight (128 entries: fp32 at
+// H = 8, V = 4 went from 253 to 292 us per call on 85 x 2^21).
+__host__ __device__ constexpr int cand_cap(int) { return 320; }
 
 // Elements of one source slot of stretch factor m: the range
 // [floor(j0/m), floor((j0+B-1)/m)] (at most floor((B-1)/m) + 2 elements)
