@@ -206,17 +206,29 @@ __device__ __forceinline__ void lse_pair_merge(float& M, float& S, float M2, flo
     M = nm;
 }
 
-// Add the lane's kV values of one plane (storage units) to its pair.
+// Add the lane's kV values of one plane (storage units) to its pair.  The
+// sum is rescaled only when some lane's maximum grows (a wave-uniform
+// branch); otherwise the rescale factor would be exp2(0) = 1 and the result
+// is the same, bitwise.  Called by the whole wave.
 template <int V>
 __device__ __forceinline__ void lse_add(const float (&x)[V], float& M, float& S, float c)
 {
-    const float nm = fmaxf(fmaxf(fmaxf(x[0], x[1]), fmaxf(x[2], x[3])), M);
-    const float base = nm == -__builtin_inff() ? 0.0f : nm;
-    float t = 0.0f;
+    const float xm = fmaxf(fmaxf(x[0], x[1]), fmaxf(x[2], x[3]));
+    if (__builtin_amdgcn_ballot_w64(xm > M)) {
+        const float nm = fmaxf(xm, M);
+        const float base = nm == -__builtin_inff() ? 0.0f : nm;
+        float t = 0.0f;
 #pragma unroll
-    for (int v = 0; v < V; ++v) t = t + __builtin_amdgcn_exp2f((x[v] - base) * c);
-    S = S * __builtin_amdgcn_exp2f((M - base) * c) + t;
-    M = nm;
+        for (int v = 0; v < V; ++v) t = t + __builtin_amdgcn_exp2f((x[v] - base) * c);
+        S = S * __builtin_amdgcn_exp2f((M - base) * c) + t;
+        M = nm;
+    } else {
+        const float base = M == -__builtin_inff() ? 0.0f : M;
+        float t = 0.0f;
+#pragma unroll
+        for (int v = 0; v < V; ++v) t = t + __builtin_amdgcn_exp2f((x[v] - base) * c);
+        S = S + t;
+    }
 }
 
 __device__ __forceinline__ uint64_t read_first_u64(uint64_t x)
