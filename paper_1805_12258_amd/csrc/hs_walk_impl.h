@@ -71,9 +71,8 @@ __host__ __device__ constexpr int strip_bins(int V) { return 64 * V; }
 // Per-wave candidate buffer (entries).  One emission call adds at most 64
 // hits per bin of the lane group; the buffer is written out before a bin's
 // hits when they might not fit, so it need not hold the 64 V hits of a
-// whole call.  Fewer entries would leave more LDS for waves but flush more
-// often, and a flush drains the wave's loads in flight (128 entries: fp32 at
-// H = 8, V = 4 went from 253 to 292 us per call on 85 x 2^21).
+// whole call.  (128 entries, which would leave more LDS for waves, made fp32
+// at H = 8, V = 4 slower: 253 -> 292 us per call on 85 x 2^21.)
 __host__ __device__ constexpr int cand_cap(int) { return 320; }
 
 // Elements of one source slot of stretch factor m: the range
@@ -156,6 +155,24 @@ __device__ __forceinline__ void static_for(F&& f)
         f(std::integral_constant<int, B>{});
         static_for<B + 1, E>(f);
     }
+}
+
+// f(integral_constant<int, m>) for every m in 2..H whose bit is set in fl,
+// in increasing m.  The bits are tested four factors at a time first: most
+// rows change few factors, and a group with no change costs one test.
+template <int H, typename F>
+__device__ __forceinline__ void for_changed(uint32_t fl, F&& f)
+{
+    static_for<0, (H - 2) / 4>([&](auto gc) {
+        constexpr int lo = 2 + 4 * decltype(gc)::value;
+        constexpr int hi = lo + 3 < H ? lo + 3 : H;
+        constexpr uint32_t gmask = ((2u << hi) - 1u) & ~((1u << lo) - 1u);
+        if (fl & gmask) {
+            static_for<lo, hi>([&](auto mc) {
+                if (fl & (1u << decltype(mc)::value)) f(mc);
+            });
+        }
+    });
 }
 
 // Wait until at most n vector-memory operations of this wave are in flight
@@ -460,10 +477,10 @@ __global__ __launch_bounds__(walk::kWThreads, (walk_min_waves<TIn, H, V>())) voi
         int c = dmas(XP);
         if constexpr (H >= 2) {
             const uint32_t fl = ir == iu.r0 ? 0xffffffffu : sload_u32(a.rowmask, ir);
-            static_for<2, H>([&](auto mc) {
+            for_changed<H>(fl, [&](auto mc) {
                 constexpr int m = decltype(mc)::value;
                 constexpr int SP = slot_pieces(m, EB, V);
-                if (fl & (1u << m)) {
+                {
                     const int at = ihead + slot_bytes(m, EB, V) > SRB ? 0 : ihead;
                     ihead = at + slot_bytes(m, EB, V);
                     const int srow = floordiv_c<m>(ir - a.c) + a.c;
@@ -639,9 +656,9 @@ __global__ __launch_bounds__(walk::kWThreads, (walk_min_waves<TIn, H, V>())) voi
         // new source rows: the lane's values, selected per bin
         if constexpr (H >= 2) {
             const uint32_t fl = r == cu.r0 ? 0xffffffffu : sload_u32(a.rowmask, r);
-            static_for<2, H>([&](auto mc) {
+            for_changed<H>(fl, [&](auto mc) {
                 constexpr int m = decltype(mc)::value;
-                if (fl & (1u << m)) {
+                {
                     const int at = ctail + slot_bytes(m, EB, V) > SRB ? 0 : ctail;
                     ctail = at + slot_bytes(m, EB, V);
                     const unsigned char* p = sring + at + lofsb[m];
