@@ -564,6 +564,33 @@ def traffic_summary(fetch_csv, write_csv, launch, cmds):
     print(json.dumps(d, indent=1))
 
 
+def profile_detect(spec, launches=6):
+    """Six hs_detect launches of one configuration on the synthetic plane
+    (for rocprofv3 counter passes); prints the candidate count."""
+    import paper_1805_12258_amd as hs
+    import synth
+    dt, H, V = spec.split(",")
+    H, V = int(H), int(V)
+    cfg = synth.SKA
+    T, N = cfg["n_temp"], cfg["n_chan"]
+    fop = synth.make_ska(device=torch.device("cuda:0"))
+    scale = 1.0
+    if dt != "f32":
+        scale = synth.PRECISION["input_scale"]
+        fop = synth.quantize(fop, {"f16": torch.float16, "bf16": torch.bfloat16}[dt], scale)
+    ta = torch.from_numpy(synth.thresholds(H, T)).cuda()
+    kw = {"schedule": 4, "bins_per_lane": V} if V > 0 else {}
+    plan = hs.Plan(T, N, H, dtype=dt, input_scale=scale, **kw)
+    cap = 1 << 23
+    out = torch.empty((cap, 2), dtype=torch.int32, device=fop.device)
+    counts = torch.empty(H + 1, dtype=torch.int64, device=fop.device)
+    for _ in range(launches):
+        hs.hs_detect(plan.handle, fop, fop.stride(0), ta, out, cap, counts)
+    torch.cuda.synchronize()
+    print(json.dumps({"profile_detect": spec, "kernel": detection_kernel(plan, dt)[0],
+                      "candidates": int(counts[-1].item())}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -591,7 +618,13 @@ def main():
                     help="write the traffic figures under profiles/ from two counter runs "
                          "(with --launch and --traffic-cmds) and exit; runs on the CPU")
     ap.add_argument("--traffic-cmds", nargs=2, default=["", ""])
+    ap.add_argument("--profile-detect", default=None, metavar="DTYPE,H,V",
+                    help="only six hs_detect launches on the 85 x 2^21 plane stored as DTYPE with H planes "
+                         "(V > 0: strip walk with V bins per lane; 0: the planner's choice), for counter runs")
     args = ap.parse_args()
+    if args.profile_detect:
+        profile_detect(args.profile_detect)
+        return
     launch = json.loads(args.launch)
     if args.traffic_summary:
         traffic_summary(args.traffic_summary[0], args.traffic_summary[1],
