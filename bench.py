@@ -438,12 +438,12 @@ def diff_leg(n_fops, steps, warmup, dev):
         out[name + "_ms"] = e0.elapsed_time(e1) / steps
     points = n_fops * T * N
     total = out["forward_ms"] + out["backward_ms"]
-    # per-point bytes: the fused forward reads the FOP once (4); the
-    # backward reads the FOP (4, forming the weights in the tile pass),
-    # writes G_1 into the gradient (4), and the second pass reads and writes
-    # the gradient (8); the tile partials written and read back (about 0.6
-    # of a plane each way) are not counted
-    fb, bb = 4, 16
+    # per-point bytes that any such pass must move: the forward reads the
+    # FOP once (4); the backward reads the FOP and writes the gradient (8).
+    # The kernels move more (counters: 5.3 and 18.5 B per point, with the
+    # staged source re-reads, the tile partials and the second pass's
+    # read-modify-write of the touched quarter of the gradient)
+    fb, bb = 4, 8
     out.update({"n_fops": n_fops, "points": points, "value": points / (total * 1e-3),
                 "unit": "points/s (forward + backward)",
                 "forward_gbs": fb * points / (out["forward_ms"] * 1e-3) / 1e9,
