@@ -669,8 +669,10 @@ def main():
     achieved = alg_bytes / (r["launch_ms"] * 1e-3) / 1e9
     tr = stored_traffic(kname, ksrc)
     traffic = None
+    fetch_ideal = None
     if tr is not None:
         traffic = tr["fetch_bytes"] + tr["write_bytes"]
+        fetch_ideal = tr["fetch_bytes"] / (points * 4)
 
     line = {
         "metric": "harmonic-summed FOP points/s + achieved HBM GB/s; batched/FP16 vs plain fp32",
@@ -691,7 +693,9 @@ def main():
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "kernel": kname, "launch_ms": r["launch_ms"],
                      "launch": "one hs_detect call: k_zero_i64 + %s + k_plane_counts" % kname,
-                     "algorithmic_bytes": alg_bytes},
+                     "algorithmic_bytes": alg_bytes, "fetch_over_ideal": fetch_ideal},
+        "seeds": {"ska": synth.SKA["seed"], "batched": synth.BATCHED["seed"],
+                  "precision": synth.PRECISION["seed"], "differentiation": synth.DIFF["seed"]},
         "autotuned": tuned,
         "cold_start": cold,
         "hbm_gbs": achieved,
