@@ -442,9 +442,10 @@ __global__ __launch_bounds__(256) void k_bwd_reduce_t(float* __restrict__ dfop, 
     const int half = (N - 1) / 2 + 1;             // bins with an m = 2 box
     const int nq = (half + 3) / 4;
     const int64_t total = (int64_t)T * nq;
+    const bool narrow = total < ((int64_t)1 << 31);   // 32-bit index arithmetic (the usual case)
     for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
          e += (int64_t)gridDim.x * blockDim.x) {
-        const int a = (int)(e / nq);
+        const int a = narrow ? (int)((uint32_t)e / (uint32_t)nq) : (int)(e / nq);
         const int b0 = (int)(e - (int64_t)a * nq) * 4;
         float add[4] = {0.0f, 0.0f, 0.0f, 0.0f};
         bool any = false;
