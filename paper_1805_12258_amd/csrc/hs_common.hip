@@ -35,13 +35,13 @@ __global__ void k_zero_i64(int64_t* p, int64_t n)
 // histogram of the plane field over the first min(total, capacity) entries
 // of each list.  Grid (x, lists); a list whose total is ~0 (a FOP the
 // batched detection rejected) is left as it is.  The list is short (a few
-// MB at most) and latency-bound: each thread keeps kPcU loads in flight (24
+// MB at most) and latency-bound: each thread keeps kPcU loads in flight (48
 // blocks cover 384 K entries in one round), every entry is one LDS atomic on
-// the block's histogram, and few blocks take part, so that few atomics meet
-// on the counts' cache line.
+// the block's histogram, and each block adds its H counts with one global
+// atomic per plane.
 constexpr int kPcThreads = 1024;
-constexpr int kPcU = 16;
-constexpr int kPcMaxBlocks = 24;
+constexpr int kPcU = 8;
+constexpr int kPcMaxBlocks = 48;
 
 __global__ __launch_bounds__(kPcThreads) void k_plane_counts(const uint64_t* out, const int64_t* out_offsets,
                                                              const int64_t* caps, int64_t cap1,
