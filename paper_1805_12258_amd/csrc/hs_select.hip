@@ -201,14 +201,16 @@ __device__ __forceinline__ void for_entries(const uint64_t* __restrict__ a, int6
 // the keys' upper 32 bits (widened to whole keys: [min << 32, max << 32 |
 // ones]).  Each thread accumulates in registers and the block reduces with
 // wave shuffles: atomics on a handful of LDS words would serialise.
+// HP: plane slots tracked per thread (4, 8 or 16, at least H).
+template <int HP>
 __global__ __launch_bounds__(kST) void k_sel_stats(const uint64_t* __restrict__ cand, int64_t n, KeyCfg cfg,
                                                    uint32_t kmask, int H, uint32_t* __restrict__ cnt,
                                                    uint64_t* __restrict__ kmin, uint64_t* __restrict__ kmax)
 {
-    __shared__ uint32_t red[3][kST / 64][kMaxH];
-    uint32_t c[kMaxH], lo[kMaxH], hi[kMaxH];
+    __shared__ uint32_t red[3][kST / 64][HP];
+    uint32_t c[HP], lo[HP], hi[HP];
 #pragma unroll
-    for (int q = 0; q < kMaxH; ++q) {
+    for (int q = 0; q < HP; ++q) {
         c[q] = 0;
         lo[q] = ~0u;
         hi[q] = 0;
@@ -219,7 +221,7 @@ __global__ __launch_bounds__(kST) void k_sel_stats(const uint64_t* __restrict__ 
         const uint32_t k = ((uint32_t)x >> cfg.s_bin) & kmask;
         const uint32_t kh = (uint32_t)(sel_key(x, cfg) >> 32);
 #pragma unroll
-        for (int q = 0; q < kMaxH; ++q) {
+        for (int q = 0; q < HP; ++q) {
             if (k == (uint32_t)q) {
                 ++c[q];
                 lo[q] = kh < lo[q] ? kh : lo[q];
@@ -229,7 +231,7 @@ __global__ __launch_bounds__(kST) void k_sel_stats(const uint64_t* __restrict__ 
     });
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
 #pragma unroll
-    for (int q = 0; q < kMaxH; ++q) {
+    for (int q = 0; q < HP; ++q) {
         if (q >= H) break;
         for (int d = 32; d >= 1; d >>= 1) {
             c[q] += (uint32_t)__shfl_xor((int)c[q], d, 64);
@@ -619,7 +621,12 @@ hipError_t select_bounded(const uint64_t* cand, int64_t n, int H, int s_bin, int
     const uint32_t kmask = (1u << s_k) - 1u;
     const KeyCfg cfg{policy, s_bin, s_bin + s_k};
     const int G = sel_blocks(n);
-    hipLaunchKernelGGL(k_sel_stats, dim3(G), dim3(kST), 0, s, cand, n, cfg, kmask, H, cnt, kmin, kmax);
+    if (H <= 4)
+        hipLaunchKernelGGL(k_sel_stats<4>, dim3(G), dim3(kST), 0, s, cand, n, cfg, kmask, H, cnt, kmin, kmax);
+    else if (H <= 8)
+        hipLaunchKernelGGL(k_sel_stats<8>, dim3(G), dim3(kST), 0, s, cand, n, cfg, kmask, H, cnt, kmin, kmax);
+    else
+        hipLaunchKernelGGL(k_sel_stats<kMaxH>, dim3(G), dim3(kST), 0, s, cand, n, cfg, kmask, H, cnt, kmin, kmax);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_sel_hist, dim3(G), dim3(kST), 0, s, cand, n, cfg, kmask, H, cnt, kmin, kmax, ph, info);
